@@ -1,0 +1,136 @@
+"""Seeded, counter-based synthetic input generators.
+
+This module is shared by the test suite, the benchmark and the oracle's
+golden-value script. It holds no arithmetic of the loop library or of the
+oracle: it only turns (seed, stream, index) into numbers.
+
+Generator
+---------
+SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+generators", OOPSLA 2014) is used as a counter-based hash: its 64-bit
+finalizer ``mix64`` is applied to ``key + (index + 1) * GOLDEN`` where
+``key = mix64(seed + stream * GOLDEN)`` and all arithmetic is modulo 2**64.
+
+Value maps (chosen so that every value sits on a short binary grid):
+
+* ``uniform_pm1``  : ``k = h >> 40`` (24 bits), value ``(k - 2**23) * 2**-23``
+  -> multiples of 2**-23 in [-1, 1).
+* ``uniform_01``   : ``k * 2**-24`` -> multiples of 2**-24 in [0, 1).
+* ``normal``       : Box-Muller in float64 from two 53-bit uniforms, rounded
+  to float32 (host only).
+* ``int_range``    : ``lo + (h >> 11) % (hi - lo)`` (small ranges only).
+
+Every integer-only map has a numpy implementation and a torch implementation
+(CPU or GPU) that produce identical bits; the torch one lets large inputs be
+generated where they will be used.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GOLDEN = 0x9E3779B97F4A7C15
+_M1 = 0xBF58476D1CE4E5B9
+_M2 = 0x94D049BB133111EB
+_MASK64 = (1 << 64) - 1
+
+__all__ = [
+    "mix64", "hash_u64", "uniform_pm1", "uniform_01", "normal", "int_range",
+    "uniform_pm1_torch", "uniform_01_torch", "hash_u64_torch",
+]
+
+
+def mix64(z: int) -> int:
+    """SplitMix64 finalizer on one Python int (mod 2**64)."""
+    z &= _MASK64
+    z = ((z ^ (z >> 30)) * _M1) & _MASK64
+    z = ((z ^ (z >> 27)) * _M2) & _MASK64
+    return z ^ (z >> 31)
+
+
+def _key(seed: int, stream: int) -> int:
+    return mix64((seed + stream * GOLDEN) & _MASK64)
+
+
+def hash_u64(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
+    """Counter-based hashes h(seed, stream, i) for i in [start, start + n)."""
+    key = np.uint64(_key(seed, stream))
+    with np.errstate(over="ignore"):
+        i = np.arange(start + 1, start + n + 1, dtype=np.uint64)
+        z = key + i * np.uint64(GOLDEN)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(_M1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(_M2)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform_pm1(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
+    """float32 values on the 2**-23 grid in [-1, 1)."""
+    k = (hash_u64(seed, stream, n, start) >> np.uint64(40)).astype(np.int64)
+    return ((k - (1 << 23)).astype(np.float64) * 2.0 ** -23).astype(np.float32)
+
+
+def uniform_01(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
+    """float32 values on the 2**-24 grid in [0, 1)."""
+    k = (hash_u64(seed, stream, n, start) >> np.uint64(40)).astype(np.float64)
+    return (k * 2.0 ** -24).astype(np.float32)
+
+
+def normal(seed: int, stream: int, n: int) -> np.ndarray:
+    """float32 standard normal values (Box-Muller in float64)."""
+    h = hash_u64(seed, stream, 2 * n)
+    u = (h >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u1 = 1.0 - u[0::2]          # (0, 1]
+    u2 = u[1::2]
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+    return z.astype(np.float32)
+
+
+def int_range(seed: int, stream: int, n: int, lo: int, hi: int) -> np.ndarray:
+    """int64 values in [lo, hi) (modulo map; fine for small ranges)."""
+    h = hash_u64(seed, stream, n) >> np.uint64(11)
+    return (h % np.uint64(hi - lo)).astype(np.int64) + lo
+
+
+def uniform01_f64(seed: int, stream: int, n: int) -> np.ndarray:
+    """float64 uniforms in [0, 1) with 53 random bits (host only)."""
+    return (hash_u64(seed, stream, n) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
+# --------------------------------------------------------------------------
+# torch versions (same bits). torch has no unsigned 64-bit arithmetic with
+# logical shifts, so int64 two's-complement wrap-around is used and every
+# right shift is followed by a mask that clears the sign-extended bits.
+# --------------------------------------------------------------------------
+
+def _to_i64(u: int) -> int:
+    u &= _MASK64
+    return u - (1 << 64) if u >= (1 << 63) else u
+
+
+def _lsr(torch, z, s: int):
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def hash_u64_torch(seed: int, stream: int, n: int, start: int = 0, device="cpu"):
+    import torch
+    key = _to_i64(_key(seed, stream))
+    z = torch.arange(start + 1, start + n + 1, dtype=torch.int64, device=device)
+    z = z * _to_i64(GOLDEN) + key
+    z = (z ^ _lsr(torch, z, 30)) * _to_i64(_M1)
+    z = (z ^ _lsr(torch, z, 27)) * _to_i64(_M2)
+    z = z ^ _lsr(torch, z, 31)
+    return z
+
+
+def uniform_pm1_torch(seed: int, stream: int, n: int, start: int = 0, device="cpu"):
+    import torch
+    k = _lsr(torch, hash_u64_torch(seed, stream, n, start, device), 40)
+    return ((k - (1 << 23)).to(torch.float64) * 2.0 ** -23).to(torch.float32)
+
+
+def uniform_01_torch(seed: int, stream: int, n: int, start: int = 0, device="cpu"):
+    import torch
+    k = _lsr(torch, hash_u64_torch(seed, stream, n, start, device), 40)
+    return (k.to(torch.float64) * 2.0 ** -24).to(torch.float32)

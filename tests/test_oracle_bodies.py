@@ -1,0 +1,248 @@
+"""Pins of the oracle's loop bodies and reductions (CPU only).
+
+Each pin rests on something other than the oracle itself: exact rational
+arithmetic, integer closed forms, fixed points and eigenmodes of the Jacobi
+iteration, integer matrices, and per-point brute force in Python scalars.
+"""
+import math
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bodies, reduce
+
+
+def _rn32_exact(v: F) -> np.float32:
+    """Round a rational to float32, nearest-even, by comparing neighbours."""
+    f = np.float32(float(v))
+    cands = [np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))]
+
+    def key(t):
+        odd = int(np.array([t], np.float32).view(np.uint32)[0]) & 1
+        return (abs(F(float(t)) - v), odd)
+    return min(cands, key=key)
+
+
+# ---------------------------------------------------------------- AXPY ----
+
+def test_fma_f32_matches_exact_rationals():
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal(3000).astype(np.float32)
+    x = (rng.standard_normal(3000) * 2.0 ** rng.integers(-30, 30, 3000)).astype(np.float32)
+    y = (rng.standard_normal(3000) * 2.0 ** rng.integers(-30, 30, 3000)).astype(np.float32)
+    for i in range(3000):
+        got = bodies.fma_f32(a[i], x[i:i + 1], y[i:i + 1])[0]
+        want = _rn32_exact(F(float(a[i])) * F(float(x[i])) + F(float(y[i])))
+        assert got == want, i
+
+
+def test_fma_f32_double_rounding_case():
+    # a*x = 2^-24 - 2^-70, y = 1 + 2^-23: float64 rounds the sum onto the
+    # float32 midpoint 1 + 2^-23 + 2^-24 and ties-to-even would go up; the
+    # exact value is below the midpoint, so the answer is 1 + 2^-23.
+    a = np.float32(1 + 2.0 ** -23)
+    x = np.float32(2.0 ** -24 * (1 - 2.0 ** -23))
+    y = np.float32(1 + 2.0 ** -23)
+    naive = np.float32(np.float64(a) * np.float64(x) + np.float64(y))
+    got = bodies.fma_f32(a, np.array([x]), np.array([y]))[0]
+    assert got == np.float32(1 + 2.0 ** -23)
+    assert naive != got
+
+
+def test_axpy_on_input_grid_is_exact():
+    # inputs on the 2^-23 grid, a = 2.5: a*x + y is a multiple of 2^-24 below 4,
+    # so it fits in 26 bits; the float32 result equals the exact value rounded once.
+    n = 4096
+    x = synth.uniform_pm1(12345, 0, n)
+    y = synth.uniform_pm1(12345, 1, n)
+    got = bodies.axpy(2.5, x, y)
+    for i in range(0, n, 97):
+        assert got[i] == _rn32_exact(F(5, 2) * F(float(x[i])) + F(float(y[i])))
+
+
+def test_sum_closed_forms():
+    for n in (0, 1, 63, 64, 65, 1000, 2 ** 20 + 3):
+        v = np.arange(n, dtype=np.float32)  # exact integers below 2^24
+        if n <= 2 ** 24:
+            assert bodies.sum_f64(v) == n * (n - 1) // 2
+    assert reduce.reduce(reduce.SUM, np.arange(10 ** 6, dtype=np.int64)) == 10 ** 6 * (10 ** 6 - 1) // 2
+
+
+def test_sum_is_exact_rational_sum():
+    rng = np.random.default_rng(2)
+    v = (rng.standard_normal(500) * 2.0 ** rng.integers(-40, 40, 500)).astype(np.float32)
+    exact = sum((F(float(t)) for t in v), F(0))
+    assert bodies.sum_f64(v) == float(exact)
+
+
+def test_reduce_ops():
+    v = np.array([3.0, -7.5, 2.25], np.float32)
+    assert reduce.reduce(reduce.MAX, v) == 3.0
+    assert reduce.reduce(reduce.MIN, v) == -7.5
+    assert reduce.reduce(reduce.MAX, v, init=10.0) == 10.0
+    assert reduce.reduce(reduce.SUM, v, init=1.0) == -1.25
+    assert reduce.reduce(reduce.MAX, np.array([], np.float32)) is None
+
+
+# -------------------------------------------------------------- Jacobi ----
+
+def _jacobi_brute(u):
+    """One float32 sweep point by point with numpy float32 scalars."""
+    H, W = u.shape
+    out = u.copy()
+    q = np.float32(0.25)
+    for i in range(1, H - 1):
+        for j in range(1, W - 1):
+            out[i, j] = ((u[i - 1, j] + u[i + 1, j]) + (u[i, j - 1] + u[i, j + 1])) * q
+    return out
+
+
+@pytest.mark.parametrize("H,W", [(5, 7), (33, 65), (3, 3), (2, 9)])
+def test_jacobi_brute_force(H, W):
+    u = synth.uniform_01(3, 0, H * W).reshape(H, W)
+    u[0, :] = u[-1, :] = 0
+    u[:, 0] = u[:, -1] = 0
+    got, res = bodies.jacobi5(u, 3)
+    ref = u.copy()
+    rr = []
+    for _ in range(3):
+        nxt = _jacobi_brute(ref)
+        m = 0.0
+        for i in range(1, H - 1):
+            for j in range(1, W - 1):
+                m = max(m, abs(float(nxt[i, j]) - float(ref[i, j])))
+        rr.append(m)
+        ref = nxt
+    assert np.array_equal(got, ref)
+    assert res.tolist() == rr
+
+
+def test_jacobi_linear_field_fixed_point():
+    N = 64
+    i, j = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    u = (i + 2 * j).astype(np.float32)
+    got, res = bodies.jacobi5(u, 5)
+    assert np.array_equal(got, u) and (res == 0).all()
+
+
+def test_jacobi_zero_and_impulse():
+    z = np.zeros((9, 9), np.float32)
+    g, r = bodies.jacobi5(z, 2)
+    assert not g.any() and (r == 0).all()
+    u = np.zeros((9, 9), np.float32)
+    u[4, 4] = 1
+    g, r = bodies.jacobi5(u, 1)
+    assert g[4, 4] == 0 and g[3, 4] == g[5, 4] == g[4, 3] == g[4, 5] == 0.25
+    assert g.sum() == 1.0 and r[0] == 1.0
+
+
+def test_jacobi_eigenmode_decay_f64():
+    N, p, q, k = 65, 2, 3, 7
+    i, j = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    h = math.pi / (N - 1)
+    u = np.sin(p * h * i) * np.sin(q * h * j)
+    lam = (math.cos(p * h) + math.cos(q * h)) / 2
+    got, _ = bodies.jacobi5(u, k, mode="f64")
+    assert np.abs(got - lam ** k * u).max() < 1e-12
+
+
+# -------------------------------------------------------------- matmul ----
+
+def test_matmul_integer_brute_force():
+    rng = np.random.default_rng(4)
+    for (M, K, N) in [(1, 1, 1), (17, 33, 65), (5, 128, 3)]:
+        A = rng.integers(-2, 3, (M, K)).astype(np.float32)
+        B = rng.integers(-2, 3, (K, N)).astype(np.float32)
+        C = bodies.matmul(A, B)
+        Ai, Bi = A.astype(int).tolist(), B.astype(int).tolist()
+        for i in range(M):
+            for j in range(N):
+                assert C[i, j] == sum(Ai[i][k] * Bi[k][j] for k in range(K))
+        # integer entries are bfloat16-exact: every variant is exact
+        assert np.array_equal(bodies.matmul_bf16(A, B), C)
+        assert np.array_equal(bodies.matmul_split3(A, B), C)
+
+
+def test_matmul_identity_and_entry():
+    A = synth.normal(5, 0, 24 * 24).reshape(24, 24)
+    I = np.eye(24, dtype=np.float32)
+    assert np.array_equal(bodies.matmul(A, I), A.astype(np.float64))
+    B = synth.normal(5, 1, 24 * 24).reshape(24, 24)
+    C = bodies.matmul(A, B)
+    for (i, j) in [(0, 0), (3, 17), (23, 23)]:
+        exact = sum((F(float(A[i, k])) * F(float(B[k, j])) for k in range(24)), F(0))
+        assert abs(bodies.matmul_entry(A, B, i, j) - float(exact)) <= abs(float(exact)) * 2.0 ** -52
+        assert abs(C[i, j] - float(exact)) <= 1e-12 * max(1.0, abs(float(exact)))
+
+
+def _bf16_exact(x: np.float32) -> np.float32:
+    """Nearest bfloat16 by brute force over the two truncation neighbours."""
+    b = int(np.array([x], np.float32).view(np.uint32)[0])
+    lo = b & 0xFFFF0000
+    hi = (lo + 0x10000) & 0xFFFFFFFF
+    vlo = np.array([lo], np.uint32).view(np.float32)[0]
+    vhi = np.array([hi], np.uint32).view(np.float32)[0]
+    if not np.isfinite(x):
+        return x
+    fx = F(float(x))
+    dlo = abs(F(float(vlo)) - fx)
+    dhi = abs(F(float(vhi)) - fx) if np.isfinite(vhi) else None
+    if dhi is None:
+        # rounding past the largest finite bf16 goes to infinity when at/above the midpoint
+        top = abs(F(float(vlo))) + F(2) ** (int(math.floor(math.log2(abs(float(vlo))))) - 7) / 2
+        return vlo if abs(fx) < top else np.float32(math.copysign(math.inf, float(x)))
+    if dlo < dhi:
+        return vlo
+    if dhi < dlo:
+        return vhi
+    return vlo if ((lo >> 16) & 1) == 0 else vhi
+
+
+def test_rne_bf16_brute_force():
+    rng = np.random.default_rng(6)
+    bits = rng.integers(0, 2 ** 32, 20000, dtype=np.uint64).astype(np.uint32)
+    x = bits.view(np.float32)
+    x = x[np.isfinite(x)]
+    # add ties, tiny, subnormal, signed zero and near-overflow values
+    extra = np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, -(1 + 2 ** -8), 0.0, -0.0, 1e-40, -3e-39,
+                      3.3895313892515355e38, 3.4028234663852886e38, -3.39e38], np.float32)
+    x = np.concatenate([x, extra])
+    got = bodies.rne_bf16(x)
+    for i in range(len(x)):
+        want = _bf16_exact(x[i])
+        assert got[i] == want or (got[i] == 0 and want == 0), (x[i], got[i], want)
+        assert np.signbit(got[i]) == np.signbit(want)
+    assert np.isnan(bodies.rne_bf16(np.array([np.nan], np.float32))[0])
+    assert bodies.rne_bf16(np.array([np.inf], np.float32))[0] == np.inf
+
+
+def test_split_bf16_reconstructs():
+    x = synth.normal(7, 0, 100000)
+    hi, lo = bodies.split_bf16(x)
+    assert (np.array(hi).view(np.uint32) & 0xFFFF == 0).all()
+    assert (np.array(lo).view(np.uint32) & 0xFFFF == 0).all()
+    rel = np.abs((hi.astype(np.float64) + lo) - x) / np.abs(x)
+    assert rel.max() <= 2.0 ** -16
+    # the residual x - hi is exact in float32
+    r32 = (x - hi).astype(np.float64)
+    assert np.array_equal(r32, x.astype(np.float64) - hi.astype(np.float64))
+
+
+def test_matvec_brute_force():
+    A = synth.uniform_pm1(8, 0, 7 * 256).reshape(7, 256)
+    x = synth.uniform_pm1(8, 1, 256)
+    y = bodies.matvec(A, x)
+    for r in range(7):
+        exact = sum((F(float(A[r, c])) * F(float(x[c])) for c in range(256)), F(0))
+        assert bodies.matvec_row(A[r], x) == float(exact)
+        # on the 2^-23 grid every product is a multiple of 2^-46 below 1, so
+        # the float64 dot product of 256 terms is exact
+        assert y[r] == float(exact)
+
+
+def test_frob_rel():
+    C = np.ones((3, 3))
+    assert bodies.frob_rel(C, C) == 0
+    assert abs(bodies.frob_rel(C * (1 + 1e-3), C) - 1e-3) < 1e-12
