@@ -1,0 +1,481 @@
+// Worksharing-loop kernels for the built-in bodies (gfx950).
+//
+// Paper: sec. 3.2 (canonical loop + worksharing with schedule, distribute and
+// collapse inside an SPMD region), sec. 5 (reduction), sec. 6 (the AXPY loop
+// body; matrix-vector, matrix multiplication and stencil kernels).
+//
+// Two kinds of kernels:
+//  * k_generic<Body>: executes exactly the iterations each (team, unit) owns
+//    under any static / static-chunk / tiled schedule, any distribute and
+//    collapse 1..3, decoding induction values as it goes. Correct for every
+//    body, used for anything the fast kernels do not cover.
+//  * fast kernels that own the same iterations with wide, coalesced access:
+//    k_stream4 (1-D, chunk 4: one f32x4 per chunk, chunks dealt over the
+//    flat unit id -- the classic grid-stride loop), k_jacobi_tile (tiles of
+//    TH x 256 points staged with their halo in LDS), k_matvec (one 64-lane
+//    wavefront per row).
+// All kernels fuse their reduction (lane -> wavefront -> LDS -> last
+// workgroup combines in float64 in workgroup order).
+#include "upir_launch.h"
+
+namespace upir {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ body functors
+struct BAxpy {
+  using Acc = float;
+  AxpyP p;
+  __device__ void operator()(int64_t, const int64_t *iv, int, int, Acc &acc, int op) const {
+    const int64_t i = iv[0];
+    const float v = __builtin_fmaf(p.a, p.x[i], p.y[i]);
+    p.y[i] = v;
+    if (op) acc = red_apply(op, acc, v);
+  }
+};
+
+template <class T, class A>
+struct BSum {
+  using Acc = A;
+  const T *x;
+  __device__ void operator()(int64_t, const int64_t *iv, int, int, Acc &acc, int op) const {
+    acc = red_apply(op, acc, (A)x[iv[0]]);
+  }
+};
+
+struct BJacobi {
+  using Acc = double;
+  JacobiP p;
+  __device__ void operator()(int64_t, const int64_t *iv, int, int, Acc &acc, int op) const {
+    const int64_t i = iv[0], j = iv[1], ld = p.ld;
+    const float *s = p.src;
+    const float v = ((s[(i - 1) * ld + j] + s[(i + 1) * ld + j]) + (s[i * ld + j - 1] + s[i * ld + j + 1])) * 0.25f;
+    p.dst[i * ld + j] = v;
+    if (op) acc = red_apply(op, acc, fabs((double)v - (double)s[i * ld + j]));
+  }
+};
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+struct BMatmul {
+  using Acc = float;
+  MatmulP p;
+  __device__ void operator()(int64_t, const int64_t *iv, int, int, Acc &, int) const {
+    const int64_t i = iv[0], j = iv[1];
+    float acc = 0.0f;
+    if (p.kind == 4) {
+      for (int64_t k = 0; k < p.K; ++k) acc = __builtin_fmaf(p.A[i * p.lda + k], p.B[k * p.ldb + j], acc);
+    } else if (p.kind == 5) {
+      for (int64_t k = 0; k < p.K; ++k)
+        acc = __builtin_fmaf(bf16_to_f32(p.ah[i * p.K + k]), bf16_to_f32(p.bh[j * p.K + k]), acc);
+    } else {
+      for (int64_t k = 0; k < p.K; ++k) {
+        const float ah = bf16_to_f32(p.ah[i * p.K + k]), al = bf16_to_f32(p.al[i * p.K + k]);
+        const float bh = bf16_to_f32(p.bh[j * p.K + k]), bl = bf16_to_f32(p.bl[j * p.K + k]);
+        acc = __builtin_fmaf(al, bh, acc);
+        acc = __builtin_fmaf(ah, bl, acc);
+        acc = __builtin_fmaf(ah, bh, acc);
+      }
+    }
+    p.C[i * p.ldc + j] = acc;
+  }
+};
+
+struct BOwner {
+  using Acc = float;
+  OwnerP p;
+  int U;
+  __device__ void operator()(int64_t k, const int64_t *, int team, int unit, Acc &, int) const {
+    p.out[k] = team * U + unit;
+  }
+};
+
+struct BCover {
+  using Acc = float;
+  CoverP p;
+  __device__ void operator()(int64_t k, const int64_t *, int, int, Acc &, int) const {
+    atomicAdd(&p.count[k], 1);
+  }
+};
+
+// ----------------------------------------------------------- generic kernel
+template <class B>
+__global__ void __launch_bounds__(1024) k_generic(LoopK L, SchedK S, RedK R, B body) {
+  using A = typename B::Acc;
+  const int team = blockIdx.x, unit = threadIdx.x;
+  A acc = red_identity<A>(R.op ? R.op : RED_SUM);
+  auto f = [&](int64_t k, const int64_t *iv) { body(k, iv, team, unit, acc, R.op); };
+  if (S.tiled)
+    for_owned_tiled(L, S, team, unit, f);
+  else
+    for_owned_untiled(L, S, team, unit, f);
+  if (R.op != RED_NONE) finish_reduction<A>(R, acc);
+}
+
+// Dynamic / guided: each team claims a range of iterations from a device
+// counter and splits it among its units in near-equal blocks. The last team
+// to finish re-arms the counter so graph replays start from zero.
+template <class B>
+__global__ void __launch_bounds__(1024) k_dynamic(LoopK L, SchedK S, RedK R, B body) {
+  using A = typename B::Acc;
+  __shared__ long long s_lo, s_hi;
+  const int team = blockIdx.x, unit = threadIdx.x;
+  A acc = red_identity<A>(R.op ? R.op : RED_SUM);
+  auto f = [&](int64_t k, const int64_t *iv) { body(k, iv, team, unit, acc, R.op); };
+  const long long n = L.n;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      long long lo, hi;
+      if (S.policy == POL_DYNAMIC) {
+        long long len = S.chunk * (long long)S.U;
+        lo = atomicAdd((unsigned long long *)S.dyn_next, (unsigned long long)len);
+        hi = lo + len < n ? lo + len : n;
+      } else {  // guided: claim max(chunk*U, remaining / (2T))
+        long long cur = __hip_atomic_load(S.dyn_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (;;) {
+          if (cur >= n) { lo = hi = n; break; }
+          long long rem = n - cur;
+          long long len = rem / (2LL * S.T);
+          long long mn = S.chunk * (long long)S.U;
+          if (len < mn) len = mn;
+          long long want = cur + len < n ? cur + len : n;
+          if (__hip_atomic_compare_exchange_strong(S.dyn_next, &cur, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)) {
+            lo = cur;
+            hi = want;
+            break;
+          }
+        }
+      }
+      s_lo = lo < n ? lo : n;
+      s_hi = hi;
+    }
+    __syncthreads();
+    const long long lo = s_lo, hi = s_hi;
+    __syncthreads();
+    if (lo >= hi) break;
+    int64_t ulo, uhi;
+    block_range(hi - lo, S.U, unit, ulo, uhi);
+    visit_range(L, lo + ulo, lo + uhi, f);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned t = atomicAdd(S.dyn_exit, 1u);
+    if (t == gridDim.x - 1) {
+      *S.dyn_next = 0;
+      *S.dyn_exit = 0u;
+      __threadfence();
+    }
+  }
+  if (R.op != RED_NONE) finish_reduction<A>(R, acc);
+}
+
+template <class B>
+static hipError_t go_generic(const B &b, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
+  if (S.policy == POL_DYNAMIC || S.policy == POL_GUIDED)
+    hipLaunchKernelGGL(k_dynamic<B>, dim3(S.T), dim3(S.U), 0, st, L, S, R, b);
+  else
+    hipLaunchKernelGGL(k_generic<B>, dim3(S.T), dim3(S.U), 0, st, L, S, R, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_generic(int32_t body, const void *payload, const LoopK &L, const SchedK &S, const RedK &R,
+                          hipStream_t st) {
+  switch (body) {
+    case 1: return go_generic(BAxpy{*(const AxpyP *)payload}, L, S, R, st);
+    case 2: {
+      const SumP &p = *(const SumP *)payload;
+      switch (p.dtype) {
+        case 1: return go_generic(BSum<float, float>{(const float *)p.x}, L, S, R, st);
+        case 2: return go_generic(BSum<double, double>{(const double *)p.x}, L, S, R, st);
+        case 3: return go_generic(BSum<int32_t, long long>{(const int32_t *)p.x}, L, S, R, st);
+        case 4: return go_generic(BSum<long long, long long>{(const long long *)p.x}, L, S, R, st);
+      }
+      return hipErrorInvalidValue;
+    }
+    case 3: return go_generic(BJacobi{*(const JacobiP *)payload}, L, S, R, st);
+    case 4:
+    case 5:
+    case 6: return go_generic(BMatmul{*(const MatmulP *)payload}, L, S, R, st);
+    case 8: return go_generic(BOwner{*(const OwnerP *)payload, S.U}, L, S, R, st);
+    case 9: return go_generic(BCover{*(const CoverP *)payload}, L, S, R, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------- 1-D streaming, chunk 4
+// Ownership: chunk m (4 iterations) belongs to flat unit m mod (T U), flat =
+// team U + unit, exactly the static-chunk-4 schedule. x and y point at the
+// element of the first iteration and are 16-byte aligned. Four owned chunks
+// are loaded before any is used to keep several loads in flight.
+template <int BODY, bool RED>
+__global__ void __launch_bounds__(1024) k_stream4(int64_t n, float a, const float *__restrict__ x,
+                                                  float *__restrict__ y, int32_t *__restrict__ cnt, RedK R) {
+  const int64_t F = (int64_t)gridDim.x * blockDim.x;
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nc = n >> 2;
+  float acc = RED ? red_identity<float>(R.op) : 0.0f;
+  const f32x4 *x4 = (const f32x4 *)x;
+  f32x4 *y4 = (f32x4 *)y;
+  auto fold = [&](float v) {
+    if (RED) acc = red_apply(R.op, acc, v);
+  };
+  int64_t m = f;
+  if (BODY == 1) {  // AXPY
+    for (; m + 3 * F < nc; m += 4 * F) {
+      f32x4 xv[4], yv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        xv[u] = x4[m + u * F];
+        yv[u] = y4[m + u * F];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        f32x4 r;
+        r.x = __builtin_fmaf(a, xv[u].x, yv[u].x);
+        r.y = __builtin_fmaf(a, xv[u].y, yv[u].y);
+        r.z = __builtin_fmaf(a, xv[u].z, yv[u].z);
+        r.w = __builtin_fmaf(a, xv[u].w, yv[u].w);
+        y4[m + u * F] = r;
+        fold(r.x); fold(r.y); fold(r.z); fold(r.w);
+      }
+    }
+    for (; m < nc; m += F) {
+      f32x4 xv = x4[m], yv = y4[m];
+      f32x4 r;
+      r.x = __builtin_fmaf(a, xv.x, yv.x);
+      r.y = __builtin_fmaf(a, xv.y, yv.y);
+      r.z = __builtin_fmaf(a, xv.z, yv.z);
+      r.w = __builtin_fmaf(a, xv.w, yv.w);
+      y4[m] = r;
+      fold(r.x); fold(r.y); fold(r.z); fold(r.w);
+    }
+    if ((n & 3) && f == nc % F) {
+      for (int64_t i = nc * 4; i < n; ++i) {
+        float r = __builtin_fmaf(a, x[i], y[i]);
+        y[i] = r;
+        fold(r);
+      }
+    }
+  } else if (BODY == 2) {  // SUM over float32
+    for (; m + 3 * F < nc; m += 4 * F) {
+      f32x4 xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = x4[m + u * F];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { fold(xv[u].x); fold(xv[u].y); fold(xv[u].z); fold(xv[u].w); }
+    }
+    for (; m < nc; m += F) {
+      f32x4 xv = x4[m];
+      fold(xv.x); fold(xv.y); fold(xv.z); fold(xv.w);
+    }
+    if ((n & 3) && f == nc % F)
+      for (int64_t i = nc * 4; i < n; ++i) fold(x[i]);
+  } else {  // COVER: count[k] += 1
+    for (; m < nc; m += F) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) atomicAdd(&cnt[4 * m + q], 1);
+    }
+    if ((n & 3) && f == nc % F)
+      for (int64_t i = nc * 4; i < n; ++i) atomicAdd(&cnt[i], 1);
+  }
+  if (RED) finish_reduction<float>(R, acc);
+}
+
+hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, const SchedK &S, const RedK &R,
+                          hipStream_t st) {
+  const bool red = R.op != RED_NONE;
+  const int64_t n = L.n, lb = L.lb[0];
+  dim3 g(S.T), b(S.U);
+  if (body == 1) {
+    const AxpyP &p = *(const AxpyP *)payload;
+    if (red)
+      hipLaunchKernelGGL((k_stream4<1, true>), g, b, 0, st, n, p.a, p.x + lb, p.y + lb, (int32_t *)nullptr, R);
+    else
+      hipLaunchKernelGGL((k_stream4<1, false>), g, b, 0, st, n, p.a, p.x + lb, p.y + lb, (int32_t *)nullptr, R);
+  } else if (body == 2) {
+    const SumP &p = *(const SumP *)payload;
+    hipLaunchKernelGGL((k_stream4<2, true>), g, b, 0, st, n, 0.0f, (const float *)p.x + lb, (float *)nullptr,
+                       (int32_t *)nullptr, R);
+  } else if (body == 9) {
+    const CoverP &p = *(const CoverP *)payload;
+    hipLaunchKernelGGL((k_stream4<9, false>), g, b, 0, st, n, 0.0f, (const float *)nullptr, (float *)nullptr,
+                       p.count, R);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------- Jacobi, LDS tiles
+// Tile = TH rows x 256 columns, anchored at multiples of (TH, 256). A team
+// stages rows i0-1 .. i0+TH and columns j0-1 .. j0+256 of src in LDS (only
+// the cells that in-box points read), then wavefront w computes tile rows
+// r = w, w + NW, ... with lane l on columns 4l .. 4l+3 -- the unit owning
+// 4-point group p/4 = r*64 + l is (p/4) mod U as the tiled schedule says.
+constexpr int JT_W = 256;          // tile width (points)
+constexpr int JT_S = JT_W + 8;     // LDS row stride (floats); core at +4
+
+template <int TH, bool RED>
+__global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP p, RedK R) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, NW = blockDim.x / WAVE;
+  const int team = xcd_team(blockIdx.x, gridDim.x);
+  const int64_t ld = p.ld;
+  const int64_t ilo = L.lb[0], ihi = L.lb[0] + L.cnt[0];  // interior rows [ilo, ihi)
+  const int64_t jlo = L.lb[1], jhi = L.lb[1] + L.cnt[1];
+  double acc = RED ? red_identity<double>(R.op) : 0.0;
+
+  auto do_tile = [&](int64_t m) {
+    const int64_t ti = S.t0[0] + m / S.nt[1], tj = S.t0[1] + m % S.nt[1];
+    const int64_t i0 = ti * TH, j0 = tj * JT_W;
+    // rows / cols read by in-box points of this tile
+    const int64_t rlo = (i0 > ilo ? i0 : ilo) - 1, rhi = (i0 + TH < ihi ? i0 + TH : ihi);      // inclusive
+    const int64_t clo = (j0 > jlo ? j0 : jlo) - 1, chi = (j0 + JT_W < jhi ? j0 + JT_W : jhi);  // inclusive
+    __syncthreads();
+    for (int rr = w; rr < TH + 2; rr += NW) {
+      const int64_t gi = i0 - 1 + rr;
+      if (gi < rlo || gi > rhi) continue;
+      const float *row = p.src + gi * ld;
+      float *lrow = lds + rr * JT_S;
+      const int64_t c0 = j0 + 4 * lane;
+      if (c0 >= clo && c0 + 3 <= chi) {
+        *(f32x4 *)(lrow + 4 + 4 * lane) = *(const f32x4 *)(row + c0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (c0 + q >= clo && c0 + q <= chi) lrow[4 + 4 * lane + q] = row[c0 + q];
+      }
+      if (lane == 0 && j0 - 1 >= clo) lrow[3] = row[j0 - 1];
+      if (lane == 1 && j0 + JT_W <= chi) lrow[4 + JT_W] = row[j0 + JT_W];
+    }
+    __syncthreads();
+    for (int r = w; r < TH; r += NW) {
+      const int64_t i = i0 + r;
+      if (i < ilo || i >= ihi) continue;
+      const float *up = lds + r * JT_S + 4, *mid = lds + (r + 1) * JT_S + 4, *dn = lds + (r + 2) * JT_S + 4;
+      const int c = 4 * lane;
+      const f32x4 N = *(const f32x4 *)(up + c), Sv = *(const f32x4 *)(dn + c), C = *(const f32x4 *)(mid + c);
+      const float Wm = mid[c - 1], Ep = mid[c + 4];
+      f32x4 v;
+      v.x = ((N.x + Sv.x) + (Wm + C.y)) * 0.25f;
+      v.y = ((N.y + Sv.y) + (C.x + C.z)) * 0.25f;
+      v.z = ((N.z + Sv.z) + (C.y + C.w)) * 0.25f;
+      v.w = ((N.w + Sv.w) + (C.z + Ep)) * 0.25f;
+      const int64_t j = j0 + c;
+      float *out = p.dst + i * ld + j;
+      const float vv[4] = {v.x, v.y, v.z, v.w};
+      const float cc[4] = {C.x, C.y, C.z, C.w};
+      if (j >= jlo && j + 3 < jhi) {
+        *(f32x4 *)out = v;
+        if (RED) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc = red_apply(R.op, acc, fabs((double)vv[q] - (double)cc[q]));
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (j + q >= jlo && j + q < jhi) {
+            out[q] = vv[q];
+            if (RED) acc = red_apply(R.op, acc, fabs((double)vv[q] - (double)cc[q]));
+          }
+        }
+      }
+    }
+  };
+
+  if (S.policy == POL_STATIC) {
+    int64_t lo, hi;
+    block_range(S.ntiles, S.T, team, lo, hi);
+    for (int64_t m = lo; m < hi; ++m) do_tile(m);
+  } else {
+    const int64_t c = S.chunk;
+    for (int64_t m0 = (int64_t)team * c; m0 < S.ntiles; m0 += (int64_t)S.T * c)
+      for (int64_t m = m0; m < m0 + c && m < S.ntiles; ++m) do_tile(m);
+  }
+  if (RED) finish_reduction<double>(R, acc);
+}
+
+bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
+  if (L.nd != 2 || !S.tiled || S.dist != DIST_TU) return false;
+  if (L.step[0] != 1 || L.step[1] != 1) return false;
+  if (S.tile[1] != JT_W) return false;
+  const int th = S.tile[0];
+  if (th != 4 && th != 8 && th != 16 && th != 32 && th != 64) return false;
+  if (S.U % WAVE != 0 || S.U < WAVE) return false;
+  if (S.policy != POL_STATIC && S.policy != POL_CHUNK) return false;
+  if ((p.ld % 4) != 0 || ((uintptr_t)p.src % 16) != 0 || ((uintptr_t)p.dst % 16) != 0) return false;
+  if (L.lb[1] < 1 || L.lb[0] < 1) return false;  // halo reads at lb-1 stay in the array
+  return true;
+}
+
+template <int TH>
+static hipError_t go_jacobi(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
+  const size_t lds = (size_t)(TH + 2) * JT_S * sizeof(float);
+  if (R.op != RED_NONE)
+    hipLaunchKernelGGL((k_jacobi_tile<TH, true>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R);
+  else
+    hipLaunchKernelGGL((k_jacobi_tile<TH, false>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_tile(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
+  switch (S.tile[0]) {
+    case 4: return go_jacobi<4>(p, L, S, R, st);
+    case 8: return go_jacobi<8>(p, L, S, R, st);
+    case 16: return go_jacobi<16>(p, L, S, R, st);
+    case 32: return go_jacobi<32>(p, L, S, R, st);
+    case 64: return go_jacobi<64>(p, L, S, R, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------- matvec, wave/row
+// The unit of a MATVEC loop is a wavefront: rows are owned by (team, wave)
+// under the schedule with U/64 units per team. Inside a row, lane l takes
+// columns 4l .. 4l+3 of every 256-column block in order, then the 64 lane
+// sums meet in a fixed butterfly.
+template <bool RED>
+__global__ void __launch_bounds__(1024) k_matvec(LoopK L, SchedK S, MatvecP p, RedK R) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  SchedK SW = S;
+  SW.U = S.U / WAVE;
+  float acc = RED ? red_identity<float>(R.op) : 0.0f;
+  const bool vec = (p.lda % 4 == 0) && ((uintptr_t)p.A % 16 == 0) && ((uintptr_t)p.x % 16 == 0);
+  auto row = [&](int64_t, const int64_t *iv) {
+    const int64_t r = iv[0];
+    const float *a = p.A + r * p.lda;
+    float s = 0.0f;
+    for (int64_t c0 = 0; c0 < p.cols; c0 += 256) {
+      const int64_t c = c0 + 4 * lane;
+      if (vec && c + 3 < p.cols) {
+        const f32x4 av = *(const f32x4 *)(a + c);
+        const f32x4 xv = *(const f32x4 *)(p.x + c);
+        s = __builtin_fmaf(av.x, xv.x, s);
+        s = __builtin_fmaf(av.y, xv.y, s);
+        s = __builtin_fmaf(av.z, xv.z, s);
+        s = __builtin_fmaf(av.w, xv.w, s);
+      } else {
+        for (int q = 0; q < 4; ++q)
+          if (c + q < p.cols) s = __builtin_fmaf(a[c + q], p.x[c + q], s);
+      }
+    }
+    s = wave_reduce(RED_SUM, s);
+    if (lane == 0) {
+      p.y[r] = s;
+      if (RED) acc = red_apply(R.op, acc, s);
+    }
+  };
+  for_owned_untiled(L, SW, blockIdx.x, w, row);
+  if (RED) finish_reduction<float>(R, acc);
+}
+
+hipError_t launch_matvec_wave(const MatvecP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
+  if (R.op != RED_NONE)
+    hipLaunchKernelGGL(k_matvec<true>, dim3(S.T), dim3(S.U), 0, st, L, S, p, R);
+  else
+    hipLaunchKernelGGL(k_matvec<false>, dim3(S.T), dim3(S.U), 0, st, L, S, p, R);
+  return hipGetLastError();
+}
+
+}  // namespace upir

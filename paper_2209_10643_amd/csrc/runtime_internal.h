@@ -1,0 +1,135 @@
+// Internal host-side state of libupir (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <set>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "upir.h"
+#include "upir_launch.h"
+
+struct Mapping {
+  uintptr_t host;
+  size_t bytes;
+  void *dev;
+  int32_t refs;
+  int32_t map;
+  int32_t access;
+};
+
+// Device scratch of one loop handle:
+//   [0]  u32 reduction ticket      [8]  f64/i64 internal result slot
+//   [16] i64 dynamic claim counter [24] u32 dynamic exit counter
+//   [32] partials (one f64 / i64 per workgroup)
+constexpr size_t SCR_TICKET = 0, SCR_RESULT = 8, SCR_DYN = 16, SCR_DYNEXIT = 24, SCR_PART = 32;
+
+struct upir_loop_obj {
+  upir_ctx *ctx = nullptr;
+  upir_loop loop{};
+  upir_sched sched{};
+  int32_t kind = 0;
+  int32_t args_dev = 1;
+  alignas(16) unsigned char args[128];
+  size_t args_size = 0;
+  bool has_red = false;
+  upir_reduction red{};
+  int64_t cnt[3] = {1, 1, 1};
+  int64_t n = 0;
+  unsigned char *scratch = nullptr;
+  int64_t part_cap = 0;
+  bool pending = false;   // async host-result reduction awaiting wait-release
+  void *ws = nullptr;     // library-owned BF16 workspace
+  size_t ws_bytes = 0;
+  int32_t sum_dtype = UPIR_DT_F32;
+  uint64_t key = 0;       // shape key for the tuning table
+};
+
+struct upir_graph_obj {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<void *> owned;  // device buffers the graph's kernels use
+};
+
+struct TaskRec {
+  upir_spmd spmd;
+  upir_loop_h loop;
+  std::vector<int64_t> preds;
+};
+
+struct AddrUse {
+  std::vector<int64_t> writers;  // tasks with out / inout on the address
+  std::vector<int64_t> all;      // every task naming the address
+};
+
+// One timing-table row: features of (loop, candidate) and the measured time.
+struct TuneRow {
+  float feat[32];
+  float log2_us;
+  int64_t loop_key;
+};
+
+struct TunedChoice {
+  upir_spmd spmd;
+  upir_sched sched;
+  double us;
+};
+
+struct ModelState;  // cost model (learned.hip)
+
+struct upir_ctx {
+  int device = -1;
+  bool none = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  upir_alloc_fn alloc = nullptr;
+  upir_free_fn free_fn = nullptr;
+  void *user = nullptr;
+  std::map<uintptr_t, Mapping> table;
+  std::string err;
+  std::set<upir_loop_obj *> loops;
+  std::set<upir_graph_obj *> graphs;
+  bool capturing = false;
+  std::vector<TaskRec> tasks;
+  std::unordered_map<uintptr_t, AddrUse> addr;
+  upir_task_trace trace{};
+  int num_cus = 256;
+  int max_lds = 160 * 1024;
+  // schedule selection
+  std::vector<TuneRow> db;
+  std::unordered_map<uint64_t, TunedChoice> tuned;
+  ModelState *model = nullptr;
+  bool model_on = false;
+  upir_loop_obj *reduce_loop = nullptr;  // cached handle for upir_reduce
+  void *trace_clock = nullptr;           // device clock of the plain executor's trace
+};
+
+// helpers shared by the runtime translation units
+upir_status upir_fail(upir_ctx *c, upir_status s, const char *fmt, ...);
+upir_status upir_hipfail(upir_ctx *c, hipError_t e, const char *what);
+void *upir_dalloc(upir_ctx *c, size_t bytes);
+void upir_dfree(upir_ctx *c, void *p);
+void upir_model_free(upir_ctx *c);
+
+namespace upir {
+struct Plan {
+  int32_t variant;
+  LoopK L;
+  SchedK S;
+  upir_spmd spmd;   // resolved teams / units
+  upir_sched sched; // resolved schedule
+};
+upir_status resolve_plan(upir_ctx *c, const upir_spmd *spmd, upir_loop_obj *lp, Plan &out);
+upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for_task);
+upir_status ensure_scratch(upir_ctx *c, upir_loop_obj *lp, int64_t parts);
+upir_status resolve_payload(upir_ctx *c, upir_loop_obj *lp, unsigned char *payload);
+uint64_t loop_shape_key(const upir_loop_obj *lp);
+// candidate schedules for the tuner / model
+int candidate_count(upir_ctx *c, const upir_loop_obj *lp);
+bool candidate_at(upir_ctx *c, const upir_loop_obj *lp, int idx, upir_spmd &sp, upir_sched &sc);
+void candidate_features(upir_ctx *c, const upir_loop_obj *lp, const upir_spmd &sp, const upir_sched &sc,
+                        float f[32]);
+bool model_pick(upir_ctx *c, upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc);
+}  // namespace upir

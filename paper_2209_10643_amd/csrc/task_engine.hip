@@ -1,0 +1,541 @@
+// Batched task engine: one persistent kernel runs a whole task graph.
+//
+// Paper: sec. 3.3 treats an offloaded kernel launch as an asynchronous task
+// ordered by depend clauses; sec. 5 lists taskwait. Launching one kernel per
+// task pays the launch and synchronisation cost the paper's evaluation
+// blames for lost time (sec. 6.2) once per task. Here a grid sized to the
+// resident capacity of the GPU runs every task of the graph:
+//
+//  * each task's loop is cut into tiles of `tile` iterations;
+//  * ready tasks sit in a queue (slot -> task id); a workgroup claims the next
+//    tile of the oldest slot that still has tiles with an atomic counter and
+//    advances the queue head once a slot is exhausted;
+//  * the workgroup that finishes a task's last tile combines the task's
+//    reduction (float64, tile order), writes its trace token and stamps, and
+//    decrements the remaining in-degree of each successor, pushing those
+//    that reach zero;
+//  * every wait is bounded: a workgroup that sees no progress for a long
+//    time raises an error flag and leaves, so the kernel always drains.
+//
+// Cross-XCD visibility uses agent-scope release / acquire (fences around the
+// counters), since the XCDs' L2 caches are not coherent with each other.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "runtime_internal.h"
+
+namespace upir {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct TaskD {
+  int32_t kind, red_op;
+  int32_t ntiles, part_base;
+  int32_t succ_begin, succ_end;
+  int32_t pred_begin, pred_end;
+  int64_t n, lb, step, tile;
+  float a;
+  int32_t vec;  // 16-byte aligned unit-step vector path allowed
+  const float *x;
+  float *y;
+  const float *A;
+  int64_t cols, lda;
+  int32_t *cnt;
+  double init;
+  double *result;
+};
+
+struct EngineD {
+  const TaskD *tasks;
+  int32_t ntasks, ninit;
+  const int32_t *succ, *pred, *init_ready, *indeg0;
+  int32_t *indeg, *tiles_done, *next_tile, *ready;
+  int32_t *ctrl;  // [0] head [1] tail [2] error
+  unsigned long long *clock;
+  double *partials;
+  uint64_t *tok, *tstart, *tdone;
+  long long spin_limit;
+};
+
+__device__ inline uint64_t mix64(uint64_t z) {
+  // SplitMix64 finalizer (Steele, Lea, Flood 2014)
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__device__ inline int ld_acq(int32_t *p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Reset the mutable engine state (a kernel, so graphs hold no memset node).
+__global__ void k_engine_reset(EngineD E) {
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x, st = gridDim.x * blockDim.x;
+  for (int i = i0; i < E.ntasks; i += st) {
+    E.indeg[i] = E.indeg0[i];
+    E.tiles_done[i] = 0;
+    E.next_tile[i] = 0;
+    E.ready[i] = i < E.ninit ? E.init_ready[i] + 1 : 0;
+  }
+  if (i0 == 0) {
+    E.ctrl[0] = 0;
+    E.ctrl[1] = E.ninit;
+    E.ctrl[2] = 0;
+    *E.clock = 0ULL;
+  }
+}
+
+// One tile of a task, executed by the whole workgroup. Returns the lane's
+// contribution to the task's reduction (already reduced over the block in
+// thread 0 by the caller).
+__device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
+  const int64_t lo = tile * t.tile;
+  const int64_t hi = lo + t.tile < t.n ? lo + t.tile : t.n;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int op = t.red_op;
+  if (t.kind == UPIR_BODY_MATVEC) {
+    const int lane = tid % WAVE, w = tid / WAVE, nw = nt / WAVE;
+    const bool vec = t.vec;
+    for (int64_t k = lo + w; k < hi; k += nw) {
+      const int64_t r = t.lb + k * t.step;
+      const float *a = t.A + r * t.lda;
+      float s = 0.0f;
+      for (int64_t c0 = 0; c0 < t.cols; c0 += 256) {
+        const int64_t c = c0 + 4 * lane;
+        if (vec && c + 3 < t.cols) {
+          const f32x4 av = *(const f32x4 *)(a + c);
+          const f32x4 xv = *(const f32x4 *)(t.x + c);
+          s = __builtin_fmaf(av.x, xv.x, s);
+          s = __builtin_fmaf(av.y, xv.y, s);
+          s = __builtin_fmaf(av.z, xv.z, s);
+          s = __builtin_fmaf(av.w, xv.w, s);
+        } else {
+          for (int q = 0; q < 4; ++q)
+            if (c + q < t.cols) s = __builtin_fmaf(a[c + q], t.x[c + q], s);
+        }
+      }
+      s = wave_reduce(RED_SUM, s);
+      if (lane == 0) {
+        t.y[r] = s;
+        if (op) acc = red_apply(op, acc, s);
+      }
+    }
+    return;
+  }
+  if (t.vec) {  // unit step, lb + lo multiple of 4, 16-byte aligned base
+    const int64_t b = t.lb + lo;
+    const int64_t len = hi - lo, nc = len >> 2;
+    if (t.kind == UPIR_BODY_AXPY) {
+      const f32x4 *x4 = (const f32x4 *)(t.x + b);
+      f32x4 *y4 = (f32x4 *)(t.y + b);
+      for (int64_t m = tid; m < nc; m += nt) {
+        const f32x4 xv = x4[m];
+        const f32x4 yv = y4[m];
+        f32x4 r;
+        r.x = __builtin_fmaf(t.a, xv.x, yv.x);
+        r.y = __builtin_fmaf(t.a, xv.y, yv.y);
+        r.z = __builtin_fmaf(t.a, xv.z, yv.z);
+        r.w = __builtin_fmaf(t.a, xv.w, yv.w);
+        y4[m] = r;
+        if (op) {
+          acc = red_apply(op, acc, r.x);
+          acc = red_apply(op, acc, r.y);
+          acc = red_apply(op, acc, r.z);
+          acc = red_apply(op, acc, r.w);
+        }
+      }
+    } else if (t.kind == UPIR_BODY_SUM) {
+      const f32x4 *x4 = (const f32x4 *)(t.x + b);
+      for (int64_t m = tid; m < nc; m += nt) {
+        const f32x4 xv = x4[m];
+        acc = red_apply(op, acc, xv.x);
+        acc = red_apply(op, acc, xv.y);
+        acc = red_apply(op, acc, xv.z);
+        acc = red_apply(op, acc, xv.w);
+      }
+    } else {
+      for (int64_t m = tid; m < nc; m += nt)
+        for (int q = 0; q < 4; ++q) atomicAdd(&t.cnt[lo + 4 * m + q], 1);
+    }
+    // ragged end of the tile
+    for (int64_t k = lo + 4 * nc + tid; k < hi; k += nt) {
+      const int64_t i = t.lb + k;
+      if (t.kind == UPIR_BODY_AXPY) {
+        const float r = __builtin_fmaf(t.a, t.x[i], t.y[i]);
+        t.y[i] = r;
+        if (op) acc = red_apply(op, acc, r);
+      } else if (t.kind == UPIR_BODY_SUM) {
+        acc = red_apply(op, acc, t.x[i]);
+      } else {
+        atomicAdd(&t.cnt[k], 1);
+      }
+    }
+    return;
+  }
+  for (int64_t k = lo + tid; k < hi; k += nt) {
+    const int64_t i = t.lb + k * t.step;
+    if (t.kind == UPIR_BODY_AXPY) {
+      const float r = __builtin_fmaf(t.a, t.x[i], t.y[i]);
+      t.y[i] = r;
+      if (op) acc = red_apply(op, acc, r);
+    } else if (t.kind == UPIR_BODY_SUM) {
+      acc = red_apply(op, acc, t.x[i]);
+    } else {
+      atomicAdd(&t.cnt[k], 1);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_engine(EngineD E) {
+  __shared__ int s_task, s_tile, s_last;
+  __shared__ float s_red[16];
+  __shared__ double s_red64[16];
+  int32_t *head = &E.ctrl[0], *tail = &E.ctrl[1], *err = &E.ctrl[2];
+  long long spins = 0;
+  int seen_h = -1, seen_t = -1;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int task = -1, tile = 0;
+      for (;;) {
+        if (ld_acq(err)) break;
+        const int h = ld_acq(head);
+        if (h >= E.ntasks) break;
+        const int tl = ld_acq(tail);
+        if (h != seen_h || tl != seen_t) {
+          seen_h = h;
+          seen_t = tl;
+          spins = 0;
+        }
+        if (h < tl) {
+          const int v = ld_acq(&E.ready[h]);
+          if (v > 0) {
+            const int t = v - 1;
+            const int k = atomicAdd(&E.next_tile[h], 1);
+            if (k < E.tasks[t].ntiles) {
+              task = t;
+              tile = k;
+              if (k == 0 && E.tstart) E.tstart[t] = atomicAdd(E.clock, 1ULL);
+              break;
+            }
+            atomicCAS(head, h, h + 1);
+            continue;
+          }
+        }
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > E.spin_limit) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+      s_task = task;
+      s_tile = tile;
+    }
+    __syncthreads();
+    const int t = s_task, k = s_tile;
+    if (t < 0) break;
+    __threadfence();  // acquire: the task's inputs were published before it became ready
+    const TaskD &d = E.tasks[t];
+    float acc = d.red_op ? red_identity<float>(d.red_op) : 0.0f;
+    run_tile(d, k, acc);
+    if (d.red_op) {
+      const float wg = block_reduce(d.red_op, acc, s_red);
+      if (threadIdx.x == 0) E.partials[d.part_base + k] = (double)wg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();  // release this tile's stores
+      const int done = atomicAdd(&E.tiles_done[t], 1);
+      s_last = (done == d.ntiles - 1);
+    }
+    __syncthreads();
+    if (s_last) {
+      __threadfence();  // acquire every tile's stores
+      if (d.red_op) {
+        double v = red_identity<double>(d.red_op);
+        for (int i = threadIdx.x; i < d.ntiles; i += blockDim.x)
+          v = red_apply(d.red_op, v,
+                        __hip_atomic_load(&E.partials[d.part_base + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        v = block_reduce(d.red_op, v, s_red64);
+        if (threadIdx.x == 0) *d.result = red_apply(d.red_op, d.init, v);
+      }
+      if (threadIdx.x == 0) {
+        if (E.tok) {
+          uint64_t hsh = mix64((uint64_t)(t + 1) * 0x9E3779B97F4A7C15ULL);
+          for (int i = d.pred_begin; i < d.pred_end; ++i)
+            hsh = mix64(hsh ^ __hip_atomic_load(&E.tok[E.pred[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          E.tok[t] = hsh;
+        }
+        if (E.tdone) E.tdone[t] = atomicAdd(E.clock, 1ULL);
+        __threadfence();  // release results, token and stamp before successors can start
+        for (int i = d.succ_begin; i < d.succ_end; ++i) {
+          const int s = E.succ[i];
+          if (atomicSub(&E.indeg[s], 1) == 1) {
+            const int slot = atomicAdd(tail, 1);
+            __hip_atomic_store(&E.ready[slot], s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Token and stamps of one task of the plain executor (runs after its kernel).
+__global__ void k_plain_trace(int32_t t, const int32_t *preds, int32_t np, uint64_t *tok, uint64_t *tstart,
+                              uint64_t *tdone, unsigned long long *clock) {
+  if (threadIdx.x != 0) return;
+  if (tstart) tstart[t] = atomicAdd(clock, 1ULL);
+  if (tok) {
+    uint64_t h = mix64((uint64_t)(t + 1) * 0x9E3779B97F4A7C15ULL);
+    for (int i = 0; i < np; ++i) h = mix64(h ^ tok[preds[i]]);
+    tok[t] = h;
+  }
+  if (tdone) tdone[t] = atomicAdd(clock, 1ULL);
+}
+
+__global__ void k_zero_u64(unsigned long long *p) { *p = 0ULL; }
+
+}  // namespace upir
+
+using namespace upir;
+
+static int64_t default_task_tile(int32_t kind) { return kind == UPIR_BODY_MATVEC ? 256 : 65536; }
+
+// tile size of a task: the schedule's tile[0] if given, else tuned / default
+static int64_t task_tile(upir_ctx *c, upir_loop_obj *lp) {
+  if (lp->sched.tile[0] > 0) return lp->sched.tile[0];
+  if (lp->sched.policy == UPIR_SCHED_AUTO) {
+    upir_spmd sp;
+    upir_sched sc;
+    auto it = c->tuned.find(lp->key ^ 0x7A5C0FFEEULL);
+    if (it != c->tuned.end() && it->second.sched.tile[0] > 0) return it->second.sched.tile[0];
+    if (c->model_on && model_pick(c, lp, sp, sc) && sc.tile[0] > 0) return sc.tile[0];
+  }
+  return default_task_tile(lp->kind);
+}
+
+// Per-context device clock for the plain executor's trace stamps.
+static upir_status plain_trace_buf(upir_ctx *c, unsigned long long **clock) {
+  if (!c->trace_clock) {
+    c->trace_clock = upir_dalloc(c, 64);
+    if (!c->trace_clock) return upir_fail(c, UPIR_ENOMEM, "trace clock");
+  }
+  *clock = (unsigned long long *)c->trace_clock;
+  return UPIR_OK;
+}
+
+upir_status upir_plain_trace(upir_ctx *c, int64_t task) {
+  unsigned long long *clock = nullptr;
+  upir_status st = plain_trace_buf(c, &clock);
+  if (st) return st;
+  if (task == 0) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, c->stream, clock);
+  const auto &preds = c->tasks[task].preds;
+  // predecessor ids travel in a small device array owned by the task list
+  int32_t *dp = nullptr;
+  if (!preds.empty()) {
+    dp = (int32_t *)upir_dalloc(c, preds.size() * 4);
+    if (!dp) return upir_fail(c, UPIR_ENOMEM, "trace preds");
+    std::vector<int32_t> hp(preds.begin(), preds.end());
+    hipError_t e = hipMemcpyAsync(dp, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      upir_dfree(c, dp);
+      return upir_hipfail(c, e, "trace preds copy");
+    }
+  }
+  hipLaunchKernelGGL(k_plain_trace, dim3(1), dim3(64), 0, c->stream, (int32_t)task, dp, (int32_t)preds.size(),
+                     c->trace.tokens, c->trace.start_stamp, c->trace.done_stamp, clock);
+  hipError_t e = hipGetLastError();
+  if (dp) {
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    upir_dfree(c, dp);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess) return upir_hipfail(c, e, "trace kernel");
+  return UPIR_OK;
+}
+
+upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **gout) {
+  const int32_t n = (int32_t)c->tasks.size();
+  if (n == 0) {
+    if (capture_only) {
+      upir_status st = upir_graph_begin(c);
+      if (st) return st;
+      upir_graph_h g;
+      st = upir_graph_end(c, &g);
+      if (st == UPIR_OK) *gout = g;
+      return st;
+    }
+    return UPIR_OK;
+  }
+  // ---- host tables
+  std::vector<TaskD> td(n);
+  std::vector<int32_t> succ_cnt(n, 0), indeg(n, 0);
+  int64_t parts = 0;
+  for (int32_t j = 0; j < n; ++j) {
+    for (int64_t p : c->tasks[j].preds) succ_cnt[p]++;
+    indeg[j] = (int32_t)c->tasks[j].preds.size();
+  }
+  std::vector<int32_t> succ_off(n + 1, 0), pred_off(n + 1, 0);
+  for (int32_t j = 0; j < n; ++j) {
+    succ_off[j + 1] = succ_off[j] + succ_cnt[j];
+    pred_off[j + 1] = pred_off[j] + indeg[j];
+  }
+  std::vector<int32_t> succ(succ_off[n]), pred(pred_off[n]), fill(n, 0);
+  for (int32_t j = 0; j < n; ++j) {
+    int32_t q = pred_off[j];
+    for (int64_t p : c->tasks[j].preds) {
+      pred[q++] = (int32_t)p;
+      succ[succ_off[p] + fill[p]++] = j;
+    }
+  }
+  std::vector<int32_t> init_ready;
+  for (int32_t j = 0; j < n; ++j)
+    if (indeg[j] == 0) init_ready.push_back(j);
+  for (int32_t j = 0; j < n; ++j) {
+    upir_loop_obj *lp = c->tasks[j].loop;
+    alignas(16) unsigned char pay[sizeof(MatmulP) + 16];
+    upir_status st = resolve_payload(c, lp, pay);
+    if (st) return st;
+    TaskD &d = td[j];
+    memset(&d, 0, sizeof d);
+    d.kind = lp->kind;
+    d.red_op = lp->has_red ? lp->red.op : 0;
+    d.n = lp->n;
+    d.lb = lp->loop.dim[0].lb;
+    d.step = lp->loop.dim[0].step;
+    int64_t tile = task_tile(c, lp);
+    if (lp->kind != UPIR_BODY_MATVEC) tile = std::max<int64_t>(4, (tile + 3) / 4 * 4);
+    d.tile = std::max<int64_t>(1, tile);
+    const int64_t nt = std::max<int64_t>(1, (d.n + d.tile - 1) / d.tile);
+    if (nt > (1LL << 30)) return upir_fail(c, UPIR_EINVAL, "task %d has too many tiles", j);
+    d.ntiles = (int32_t)nt;
+    d.part_base = (int32_t)parts;
+    if (d.red_op) parts += nt;
+    d.succ_begin = succ_off[j];
+    d.succ_end = succ_off[j + 1];
+    d.pred_begin = pred_off[j];
+    d.pred_end = pred_off[j + 1];
+    if (lp->has_red) {
+      d.init = lp->red.init;
+      d.result = (double *)(lp->red.result_on_host ? (void *)(lp->scratch + SCR_RESULT) : lp->red.result);
+    }
+    if (lp->kind == UPIR_BODY_AXPY) {
+      const AxpyP &p = *(const AxpyP *)pay;
+      d.a = p.a;
+      d.x = p.x;
+      d.y = p.y;
+      d.vec = d.step == 1 && ((uintptr_t)(p.x + d.lb) % 16 == 0) && ((uintptr_t)(p.y + d.lb) % 16 == 0);
+    } else if (lp->kind == UPIR_BODY_SUM) {
+      const SumP &p = *(const SumP *)pay;
+      if (p.dtype != UPIR_DT_F32) return upir_fail(c, UPIR_EUNSUPPORTED, "batched SUM tasks take float32 data");
+      d.x = (const float *)p.x;
+      d.vec = d.step == 1 && ((uintptr_t)(d.x + d.lb) % 16 == 0);
+    } else if (lp->kind == UPIR_BODY_MATVEC) {
+      const MatvecP &p = *(const MatvecP *)pay;
+      d.A = p.A;
+      d.x = p.x;
+      d.y = p.y;
+      d.cols = p.cols;
+      d.lda = p.lda;
+      d.vec = (p.lda % 4 == 0) && ((uintptr_t)p.A % 16 == 0) && ((uintptr_t)p.x % 16 == 0);
+    } else {
+      const CoverP &p = *(const CoverP *)pay;
+      d.cnt = p.count;
+      d.vec = d.step == 1 && d.lb == 0;
+    }
+  }
+  if (parts > (1LL << 31)) return upir_fail(c, UPIR_EINVAL, "too many reduction tiles");
+  // ---- device buffer: [tasks][succ][pred][init_ready][indeg0] static, then mutable state
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_tasks = al(sizeof(TaskD) * n), b_succ = al(4 * succ.size() + 4), b_pred = al(4 * pred.size() + 4);
+  const size_t b_init = al(4 * init_ready.size() + 4), b_i32 = al(4 * (size_t)n);
+  const size_t static_bytes = b_tasks + b_succ + b_pred + b_init + b_i32;
+  const size_t total = static_bytes + 4 * b_i32 + al(64) + al(8 * (size_t)std::max<int64_t>(parts, 1));
+  std::vector<unsigned char> host(static_bytes, 0);
+  size_t o = 0;
+  memcpy(&host[o], td.data(), sizeof(TaskD) * n);
+  o += b_tasks;
+  if (!succ.empty()) memcpy(&host[o], succ.data(), 4 * succ.size());
+  o += b_succ;
+  if (!pred.empty()) memcpy(&host[o], pred.data(), 4 * pred.size());
+  o += b_pred;
+  if (!init_ready.empty()) memcpy(&host[o], init_ready.data(), 4 * init_ready.size());
+  o += b_init;
+  memcpy(&host[o], indeg.data(), 4 * (size_t)n);
+  unsigned char *dev = (unsigned char *)upir_dalloc(c, total);
+  if (!dev) return upir_fail(c, UPIR_ENOMEM, "task engine tables (%zu bytes)", total);
+  hipError_t e = hipMemcpyAsync(dev, host.data(), static_bytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    upir_dfree(c, dev);
+    return upir_hipfail(c, e, "task table copy");
+  }
+  EngineD E{};
+  o = 0;
+  E.tasks = (const TaskD *)(dev + o);
+  o += b_tasks;
+  E.succ = (const int32_t *)(dev + o);
+  o += b_succ;
+  E.pred = (const int32_t *)(dev + o);
+  o += b_pred;
+  E.init_ready = (const int32_t *)(dev + o);
+  o += b_init;
+  E.indeg0 = (const int32_t *)(dev + o);
+  o += b_i32;
+  E.indeg = (int32_t *)(dev + o);
+  o += b_i32;
+  E.tiles_done = (int32_t *)(dev + o);
+  o += b_i32;
+  E.next_tile = (int32_t *)(dev + o);
+  o += b_i32;
+  E.ready = (int32_t *)(dev + o);
+  o += b_i32;
+  E.ctrl = (int32_t *)(dev + o);
+  E.clock = (unsigned long long *)(dev + o + 16);
+  o += al(64);
+  E.partials = (double *)(dev + o);
+  E.ntasks = n;
+  E.ninit = (int32_t)init_ready.size();
+  E.tok = c->trace.tokens;
+  E.tstart = c->trace.start_stamp;
+  E.tdone = c->trace.done_stamp;
+  E.spin_limit = 1LL << 22;
+  const char *gs = getenv("UPIR_ENGINE_GRID");
+  int grid = c->num_cus * 4;
+  if (gs && atoi(gs) > 0) grid = atoi(gs);
+  const int rgrid = std::max(1, std::min(1024, (n + 255) / 256));
+  upir_status st = UPIR_OK;
+  if (capture_only) {
+    st = upir_graph_begin(c);
+    if (st) {
+      upir_dfree(c, dev);
+      return st;
+    }
+  }
+  hipLaunchKernelGGL(k_engine_reset, dim3(rgrid), dim3(256), 0, c->stream, E);
+  hipLaunchKernelGGL(k_engine, dim3(grid), dim3(256), 0, c->stream, E);
+  e = hipGetLastError();
+  if (capture_only) {
+    upir_graph_h g = nullptr;
+    st = upir_graph_end(c, &g);
+    if (e != hipSuccess && st == UPIR_OK) {
+      upir_graph_destroy(c, g);
+      st = upir_hipfail(c, e, "task engine launch");
+    }
+    if (st == UPIR_OK) {
+      g->owned.push_back(dev);
+      *gout = g;
+    } else {
+      upir_dfree(c, dev);
+    }
+    return st;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  int32_t ctrl[3] = {0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpy(ctrl, E.ctrl, sizeof ctrl, hipMemcpyDeviceToHost);
+  upir_dfree(c, dev);
+  if (e != hipSuccess) return upir_hipfail(c, e, "task engine");
+  if (ctrl[2]) return upir_fail(c, UPIR_EDEPEND, "task graph did not drain (head %d, tail %d of %d)", ctrl[0], ctrl[1], n);
+  return UPIR_OK;
+}

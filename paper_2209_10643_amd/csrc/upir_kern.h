@@ -1,0 +1,329 @@
+// Internal device-side definitions shared by the runtime and the kernels.
+//
+// Worksharing (paper sec. 3.2): a loop of n collapsed iterations runs in an
+// SPMD region of T teams (workgroups) x U units (work-items). The functions
+// here enumerate the iterations a (team, unit) pair owns under each schedule;
+// every kernel that honours a schedule goes through them or through a fast
+// path that owns exactly the same iterations.
+//
+// Reduction (sec. 5; sec. 3.1 on fusing a reduction with the region's
+// barrier): lane values are combined inside a wavefront with cross-lane
+// shuffles, across the wavefronts of a workgroup through LDS, and across
+// workgroups in float64 (or exact int64) by the last workgroup to arrive,
+// which reads every workgroup's partial in a fixed order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace upir {
+
+enum : int32_t { POL_STATIC = 0, POL_CHUNK = 1, POL_DYNAMIC = 2, POL_GUIDED = 3 };
+enum : int32_t { DIST_TU = 0, DIST_T = 1, DIST_U = 2 };
+enum : int32_t { RED_NONE = 0, RED_SUM = 1, RED_MAX = 2, RED_MIN = 3 };
+
+constexpr int WAVE = 64;
+constexpr int UNIT_GROUP = 4;  // consecutive points per unit slice inside a tile
+
+struct LoopK {
+  int32_t nd;
+  int32_t pad_;
+  int64_t lb[3], step[3], cnt[3];
+  int64_t n;  // product of cnt
+};
+
+struct SchedK {
+  int32_t policy, dist;
+  int64_t chunk;
+  int32_t tiled;
+  int32_t tile[3];
+  int64_t t0[3], nt[3], ntiles;  // tile grid (tiled only)
+  int32_t T, U;                   // teams, units of the launch
+  long long *dyn_next;            // DYNAMIC / GUIDED claim counter (self-resetting)
+  unsigned *dyn_exit;             // workgroups that finished claiming
+};
+
+struct RedK {
+  int32_t op;                 // RED_*
+  int32_t is_int;             // accumulate exactly in int64
+  double init;
+  long long init_i;
+  void *result;               // device double* or long long*
+  double *partials;           // one slot per workgroup (reinterpreted for int64)
+  unsigned *ticket;           // arrivals; reset to 0 by the last workgroup
+};
+
+// ------------------------------------------------------------------ helpers
+__host__ __device__ inline void block_range(int64_t n, int64_t parts, int64_t p, int64_t &lo, int64_t &hi) {
+  int64_t q = n / parts, r = n % parts;
+  lo = p * q + (p < r ? p : r);
+  hi = lo + q + (p < r ? 1 : 0);
+}
+
+// Team id of this workgroup. Teams are logical; hardware hands workgroups
+// to the 8 XCDs round-robin, so consecutive team ids are placed on the same
+// XCD (each XCD owns a contiguous run of team ids) to share its L2.
+__device__ inline int xcd_team(int b, int G) {
+  const int X = 8;
+  int q = G / X, r = G % X;
+  int x = b % X, i = b / X;
+  int base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  return base + i;
+}
+
+// Collapsed index -> induction values (row-major).
+__device__ inline void decode(const LoopK &L, int64_t k, int64_t iv[3]) {
+  if (L.nd == 1) {
+    iv[0] = L.lb[0] + k * L.step[0];
+  } else if (L.nd == 2) {
+    int64_t a = k / L.cnt[1], b = k - a * L.cnt[1];
+    iv[0] = L.lb[0] + a * L.step[0];
+    iv[1] = L.lb[1] + b * L.step[1];
+  } else {
+    int64_t c = k % L.cnt[2];
+    int64_t t = k / L.cnt[2];
+    int64_t b = t % L.cnt[1];
+    int64_t a = t / L.cnt[1];
+    iv[0] = L.lb[0] + a * L.step[0];
+    iv[1] = L.lb[1] + b * L.step[1];
+    iv[2] = L.lb[2] + c * L.step[2];
+  }
+}
+
+// Visit k in [lo, hi) with induction values advanced as an odometer.
+template <class F>
+__device__ inline void visit_range(const LoopK &L, int64_t lo, int64_t hi, F &f) {
+  if (lo >= hi) return;
+  int64_t iv[3] = {0, 0, 0};
+  int64_t idx[3] = {0, 0, 0};
+  int64_t r = lo;
+  for (int d = L.nd - 1; d >= 0; --d) {
+    idx[d] = r % L.cnt[d];
+    r /= L.cnt[d];
+    iv[d] = L.lb[d] + idx[d] * L.step[d];
+  }
+  for (int64_t k = lo; k < hi; ++k) {
+    f(k, iv);
+    for (int d = L.nd - 1; d >= 0; --d) {
+      ++idx[d];
+      iv[d] += L.step[d];
+      if (idx[d] < L.cnt[d]) break;
+      idx[d] = 0;
+      iv[d] = L.lb[d];
+    }
+  }
+}
+
+// Every iteration owned by (team, unit) under static / static-chunk (untiled).
+template <class F>
+__device__ inline void for_owned_untiled(const LoopK &L, const SchedK &S, int team, int unit, F &f) {
+  const int64_t n = L.n;
+  if (S.policy == POL_STATIC) {
+    if (S.dist == DIST_U) {
+      int64_t lo, hi;
+      block_range(n, S.U, unit, lo, hi);
+      visit_range(L, lo, hi, f);
+      return;
+    }
+    int64_t tlo, thi;
+    block_range(n, S.T, team, tlo, thi);
+    if (S.dist == DIST_T) {
+      if (unit == 0) visit_range(L, tlo, thi, f);
+      return;
+    }
+    int64_t ulo, uhi;
+    block_range(thi - tlo, S.U, unit, ulo, uhi);
+    visit_range(L, tlo + ulo, tlo + uhi, f);
+  } else {  // POL_CHUNK
+    const int64_t c = S.chunk;
+    int64_t first, stride;
+    if (S.dist == DIST_TU) {
+      first = (int64_t)team * S.U + unit;
+      stride = (int64_t)S.T * S.U;
+    } else if (S.dist == DIST_T) {
+      if (unit != 0) return;
+      first = team;
+      stride = S.T;
+    } else {
+      first = unit;
+      stride = S.U;
+    }
+    for (int64_t m = first; m * c < n; m += stride) {
+      int64_t lo = m * c, hi = lo + c < n ? lo + c : n;
+      visit_range(L, lo, hi, f);
+    }
+  }
+}
+
+// Tiled schedules: tiles -> teams by policy, 4-point groups -> units.
+template <class F>
+__device__ inline void for_owned_tile(const LoopK &L, const SchedK &S, int64_t m, int unit, F &f) {
+  int64_t tc[3] = {0, 0, 0};
+  int64_t rem = m;
+  for (int d = L.nd - 1; d >= 0; --d) {
+    tc[d] = S.t0[d] + rem % S.nt[d];
+    rem /= S.nt[d];
+  }
+  int64_t vol = 1;
+  for (int d = 0; d < L.nd; ++d) vol *= S.tile[d];
+  for (int64_t g = unit; g * UNIT_GROUP < vol; g += S.U) {
+    for (int q = 0; q < UNIT_GROUP; ++q) {
+      int64_t p = g * UNIT_GROUP + q;
+      if (p >= vol) break;
+      int64_t off[3] = {0, 0, 0};
+      int64_t pr = p;
+      for (int d = L.nd - 1; d >= 0; --d) {
+        off[d] = pr % S.tile[d];
+        pr /= S.tile[d];
+      }
+      int64_t iv[3] = {0, 0, 0};
+      bool in = true;
+      int64_t k = 0;
+      for (int d = 0; d < L.nd; ++d) {
+        iv[d] = tc[d] * S.tile[d] + off[d];
+        int64_t ub = L.lb[d] + L.cnt[d];  // unit steps
+        in = in && iv[d] >= L.lb[d] && iv[d] < ub;
+        k = k * L.cnt[d] + (iv[d] - L.lb[d]);
+      }
+      if (in) f(k, iv);
+    }
+  }
+}
+
+template <class F>
+__device__ inline void for_owned_tiled(const LoopK &L, const SchedK &S, int team, int unit, F &f) {
+  if (S.policy == POL_STATIC) {
+    int64_t lo, hi;
+    block_range(S.ntiles, S.T, team, lo, hi);
+    for (int64_t m = lo; m < hi; ++m) for_owned_tile(L, S, m, unit, f);
+  } else {
+    const int64_t c = S.chunk;
+    for (int64_t m0 = (int64_t)team * c; m0 < S.ntiles; m0 += (int64_t)S.T * c)
+      for (int64_t m = m0; m < m0 + c && m < S.ntiles; ++m) for_owned_tile(L, S, m, unit, f);
+  }
+}
+
+// ---------------------------------------------------- wavefront reductions
+template <class T> struct OpSum { __device__ static T apply(T a, T b) { return a + b; } };
+template <class T> struct OpMax { __device__ static T apply(T a, T b) { return a > b ? a : b; } };
+template <class T> struct OpMin { __device__ static T apply(T a, T b) { return a < b ? a : b; } };
+
+template <class T>
+__device__ inline T red_apply(int op, T a, T b) {
+  if (op == RED_SUM) return a + b;
+  if (op == RED_MAX) return a > b ? a : b;
+  return a < b ? a : b;
+}
+
+template <class T>
+__device__ inline T red_identity(int op);
+template <> __device__ inline float red_identity<float>(int op) {
+  return op == RED_SUM ? 0.0f : (op == RED_MAX ? -__builtin_inff() : __builtin_inff());
+}
+template <> __device__ inline double red_identity<double>(int op) {
+  return op == RED_SUM ? 0.0 : (op == RED_MAX ? -__builtin_inf() : __builtin_inf());
+}
+template <> __device__ inline long long red_identity<long long>(int op) {
+  return op == RED_SUM ? 0LL : (op == RED_MAX ? (long long)0x8000000000000000ULL : 0x7FFFFFFFFFFFFFFFLL);
+}
+
+// Butterfly over the 64 lanes (fixed tree: xor 32, 16, ..., 1).
+template <class T>
+__device__ inline T wave_reduce(int op, T v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v = red_apply(op, v, __shfl_xor(v, s, WAVE));
+  return v;
+}
+
+// Block reduce: every thread passes its value; returns the block value in
+// thread 0 (other threads get an unspecified value). `lds` holds >= 16 T.
+template <class T>
+__device__ inline T block_reduce(int op, T v, T *lds) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int nw = (blockDim.x + WAVE - 1) / WAVE;
+  v = wave_reduce(op, v);
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  T r = red_identity<T>(op);
+  if (threadIdx.x < WAVE) {
+    r = threadIdx.x < nw ? lds[threadIdx.x] : red_identity<T>(op);
+    r = wave_reduce(op, r);
+  }
+  return r;
+}
+
+// Cross-workgroup combine. Thread 0 of every workgroup holds `wg` (float64
+// for float data). The last workgroup to arrive folds every partial in
+// workgroup order, adds `init`, writes the result and re-arms the ticket.
+__device__ inline void combine_f64(const RedK &R, double wg, double *lds) {
+  __shared__ unsigned s_last;
+  const int G = gridDim.x;
+  if (threadIdx.x == 0) {
+    R.partials[blockIdx.x] = wg;
+    __threadfence();
+    unsigned t = atomicAdd(R.ticket, 1u);
+    s_last = (t == (unsigned)(G - 1));
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double v = red_identity<double>(R.op);
+  for (int i = threadIdx.x; i < G; i += blockDim.x)
+    v = red_apply(R.op, v, __hip_atomic_load(&R.partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  v = block_reduce(R.op, v, lds);
+  if (threadIdx.x == 0) {
+    *(double *)R.result = red_apply(R.op, R.init, v);
+    *R.ticket = 0u;
+    __threadfence();
+  }
+}
+
+__device__ inline void combine_i64(const RedK &R, long long wg, long long *lds) {
+  __shared__ unsigned s_last;
+  const int G = gridDim.x;
+  long long *parts = (long long *)R.partials;
+  if (threadIdx.x == 0) {
+    parts[blockIdx.x] = wg;
+    __threadfence();
+    unsigned t = atomicAdd(R.ticket, 1u);
+    s_last = (t == (unsigned)(G - 1));
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  long long v = red_identity<long long>(R.op);
+  for (int i = threadIdx.x; i < G; i += blockDim.x)
+    v = red_apply(R.op, v, __hip_atomic_load(&parts[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  v = block_reduce(R.op, v, lds);
+  if (threadIdx.x == 0) {
+    *(long long *)R.result = red_apply(R.op, R.init_i, v);
+    *R.ticket = 0u;
+    __threadfence();
+  }
+}
+
+// Lane value -> workgroup value -> cross-workgroup combine.
+template <class A>
+__device__ inline void finish_reduction(const RedK &R, A lane);
+
+template <>
+__device__ inline void finish_reduction<float>(const RedK &R, float lane) {
+  __shared__ float lf[16];
+  __shared__ double ld[16];
+  float wg = block_reduce(R.op, lane, lf);
+  combine_f64(R, (double)wg, ld);
+}
+template <>
+__device__ inline void finish_reduction<double>(const RedK &R, double lane) {
+  __shared__ double ld[16];
+  double wg = block_reduce(R.op, lane, ld);
+  combine_f64(R, wg, ld);
+}
+template <>
+__device__ inline void finish_reduction<long long>(const RedK &R, long long lane) {
+  __shared__ long long li[16];
+  long long wg = block_reduce(R.op, lane, li);
+  combine_i64(R, wg, li);
+}
+
+}  // namespace upir

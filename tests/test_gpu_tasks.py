@@ -1,0 +1,208 @@
+"""GPU parity of tasks with depend: plain (one launch per task) and batched
+(one persistent kernel) executors against the oracle's index-order run.
+
+Bit-exact: AXPY outputs, MATVEC outputs between the two executors, tokens
+(the chain over each task's predecessors, which a stale read or a violated
+edge would change), coverage counts. Stamps: every edge i -> j has
+done[i] < start[j]. SUM results within 1e-5 * sum|x|, MATVEC normwise 1e-5.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bodies, tasks as otasks
+from paper_2209_10643_amd import helpers as H
+from paper_2209_10643_amd import upir as U
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def note(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    U.lib()
+    c = H.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def make_workload(seed, n, lmin=8, lmax=16, p_edge=None):
+    """Task kinds uniform over AXPY / SUM / MATVEC, lengths floor(2^U) with
+    U uniform in [lmin, lmax], edges i < j with probability 4/(n-1)."""
+    kinds = synth.int_range(seed, 100, n, 0, 3)
+    u = synth.uniform01_f64(seed, 101, n)
+    lens = np.floor(2.0 ** (lmin + (lmax - lmin) * u)).astype(np.int64)
+    p = p_edge if p_edge is not None else 4.0 / max(1, n - 1)
+    preds = []
+    for j in range(n):
+        r = synth.uniform01_f64(seed, 1000 + j, max(j, 1))[:j]
+        preds.append([int(i) for i in np.nonzero(r < p)[0]])
+    specs = []
+    for j in range(n):
+        kind = ("axpy", "sum", "matvec")[int(kinds[j])]
+        L = int(lens[j])
+        if kind == "axpy":
+            specs.append((kind, {"a": 2.5, "x": synth.uniform_pm1(seed, 10 * j + 1, L),
+                                 "y": synth.uniform_pm1(seed, 10 * j + 2, L)}))
+        elif kind == "sum":
+            specs.append((kind, {"x": synth.uniform_pm1(seed, 10 * j + 1, L)}))
+        else:
+            rows = max(1, L // 256)
+            specs.append((kind, {"A": synth.uniform_pm1(seed, 10 * j + 1, rows * 256).reshape(rows, 256),
+                                 "x": synth.uniform_pm1(seed, 10 * j + 2, 256)}))
+    return specs, preds
+
+
+def build_tasks(ctx, specs, preds, tile=0):
+    tok = torch.zeros(len(specs), dtype=torch.int64, device="cuda")
+    handles, bufs = [], []
+    sched = H.make_sched(U.UPIR_SCHED_AUTO, tile=(tile,)) if tile else None
+    for j, (kind, a) in enumerate(specs):
+        if kind == "axpy":
+            tx, ty = dev(a["x"]), dev(a["y"])
+            args = U.upir_axpy_args(2.5, 0, tx.data_ptr(), ty.data_ptr())
+            lp = ctx.loop(U.UPIR_BODY_AXPY, args, [(0, len(a["x"]), 1)], sched)
+            bufs.append((tx, ty))
+        elif kind == "sum":
+            tx, r = dev(a["x"]), torch.zeros(1, dtype=torch.float64, device="cuda")
+            args = U.upir_sum_args(tx.data_ptr(), U.UPIR_DT_F32, 0)
+            lp = ctx.loop(U.UPIR_BODY_SUM, args, [(0, len(a["x"]), 1)], sched, H.make_red(U.UPIR_RED_SUM, r.data_ptr()))
+            bufs.append((tx, r))
+        else:
+            tA, tx = dev(a["A"]), dev(a["x"])
+            ty = torch.zeros(a["A"].shape[0], device="cuda")
+            args = U.upir_matvec_args(tA.data_ptr(), tx.data_ptr(), ty.data_ptr(), 256, 256)
+            lp = ctx.loop(U.UPIR_BODY_MATVEC, args, [(0, a["A"].shape[0], 1)], sched)
+            bufs.append((tA, tx, ty))
+        handles.append(lp)
+    base = tok.data_ptr()
+    for j in range(len(specs)):
+        deps = [(base + 8 * j, U.UPIR_DEP_OUT)] + [(base + 8 * i, U.UPIR_DEP_IN) for i in preds[j]]
+        assert ctx.task(handles[j], deps) == j
+        assert ctx.task_preds(j) == preds[j]
+    return handles, bufs, tok
+
+
+def collect(specs, bufs):
+    out = []
+    for (kind, _), b in zip(specs, bufs):
+        if kind == "axpy":
+            out.append(b[1].cpu().numpy())
+        elif kind == "sum":
+            out.append(float(b[1].item()))
+        else:
+            out.append(b[2].cpu().numpy())
+    return out
+
+
+def check_against_oracle(specs, got):
+    want = otasks.run_in_order(specs)
+    for (kind, a), g, w in zip(specs, got, want):
+        if kind == "axpy":
+            assert np.array_equal(g, w["y"])
+        elif kind == "sum":
+            assert abs(g - w["s"]) <= 1e-5 * bodies.sum_abs_f64(a["x"])
+        else:
+            assert bodies.frob_rel(g.astype(np.float64), w["y"]) <= 1e-5
+
+
+def stamps_ok(preds, start, done):
+    for j, pj in enumerate(preds):
+        for i in pj:
+            assert done[i] < start[j], (i, j, done[i], start[j])
+        assert start[j] <= done[j]
+
+
+@pytest.mark.parametrize("mode", [U.UPIR_TASKWAIT_PLAIN, U.UPIR_TASKWAIT_BATCHED])
+@pytest.mark.parametrize("seed,n,tile", [(1, 64, 0), (2, 200, 0), (3, 200, 4096)])
+def test_tasks_match_oracle(ctx, mode, seed, n, tile):
+    note(f"tasks mode={mode} seed={seed} n={n} tile={tile}")
+    specs, preds = make_workload(seed, n)
+    handles, bufs, tok = build_tasks(ctx, specs, preds, tile)
+    start = torch.zeros(n, dtype=torch.int64, device="cuda")
+    done = torch.zeros(n, dtype=torch.int64, device="cuda")
+    ctx.set_trace(tok.data_ptr(), start.data_ptr(), done.data_ptr())
+    ctx.taskwait(mode)
+    ctx.set_trace()
+    got = collect(specs, bufs)
+    check_against_oracle(specs, got)
+    want_tok = otasks.tokens(preds)
+    got_tok = [int(v) & (2 ** 64 - 1) for v in tok.cpu().numpy().tolist()]
+    assert got_tok == want_tok
+    stamps_ok(preds, start.cpu().numpy(), done.cpu().numpy())
+    for h in handles:
+        ctx.free(h)
+
+
+def test_plain_and_batched_agree_bitwise(ctx):
+    specs, preds = make_workload(4, 150)
+    res = []
+    for mode in (U.UPIR_TASKWAIT_PLAIN, U.UPIR_TASKWAIT_BATCHED):
+        handles, bufs, tok = build_tasks(ctx, specs, preds)
+        ctx.taskwait(mode)
+        res.append(collect(specs, bufs))
+        for h in handles:
+            ctx.free(h)
+    for (kind, _), a, b in zip(specs, res[0], res[1]):
+        if kind != "sum":
+            assert np.array_equal(a, b)
+
+
+def test_batched_graph_replays(ctx):
+    specs, preds = make_workload(5, 120, lmax=14)
+    handles, bufs, tok = build_tasks(ctx, specs, preds)
+    ctx.set_trace(tok.data_ptr())
+    g = ctx.taskwait_graph(U.UPIR_TASKWAIT_BATCHED)
+    ctx.set_trace()
+    want_tok = otasks.tokens(preds)
+    cur = [dict(a) for _, a in specs]
+    for rep in range(3):
+        tok.zero_()
+        torch.cuda.synchronize()
+        ctx.graph_launch(g)
+        ctx.sync()
+        # every replay applies each AXPY once more
+        for j, (kind, a) in enumerate(specs):
+            if kind == "axpy":
+                cur[j]["y"] = bodies.axpy(2.5, a["x"], cur[j]["y"])
+                assert np.array_equal(bufs[j][1].cpu().numpy(), cur[j]["y"])
+        got_tok = [int(v) & (2 ** 64 - 1) for v in tok.cpu().numpy().tolist()]
+        assert got_tok == want_tok
+    ctx.graph_destroy(g)
+    for h in handles:
+        ctx.free(h)
+
+
+@pytest.mark.parametrize("mode", [U.UPIR_TASKWAIT_PLAIN, U.UPIR_TASKWAIT_BATCHED])
+def test_task_coverage(ctx, mode):
+    n_tasks = 50
+    lens = [int(v) for v in np.floor(2.0 ** (4 + 12 * synth.uniform01_f64(6, 0, n_tasks)))]
+    cnts, handles = [], []
+    for j, L in enumerate(lens):
+        c = torch.zeros(L, dtype=torch.int32, device="cuda")
+        lp = ctx.loop(U.UPIR_BODY_COVER, U.upir_cover_args(c.data_ptr()), [(0, L, 1)],
+                      H.make_sched(U.UPIR_SCHED_AUTO, tile=(64,)))
+        ctx.task(lp, [(0x1000, U.UPIR_DEP_INOUT)] if j % 3 == 0 else [])
+        cnts.append(c)
+        handles.append(lp)
+    ctx.taskwait(mode)
+    for c in cnts:
+        assert (c.cpu().numpy() == 1).all()
+    for h in handles:
+        ctx.free(h)
+
+
+def test_empty_taskwait(ctx):
+    ctx.taskwait(U.UPIR_TASKWAIT_BATCHED)
+    ctx.taskwait(U.UPIR_TASKWAIT_PLAIN)
