@@ -1,0 +1,422 @@
+"""Benchmark of the UPIR data-parallel loop library on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--configs 1,0,2,3,4]
+                    [--no-cpu-baseline]
+
+One step = one pass of the headline workload: a 4096 x 4096 float32 Jacobi
+5-point stencil, 100 sweeps, each sweep a collapse(2) worksharing loop with a
+fused float64 max-residual reduction, the 100 sweeps replayed as one HIP
+graph with the grids resident in HBM. ``value`` = algorithmic HBM bytes of a
+step (per sweep: read the 4096^2 grid once, write the interior once) / time.
+
+The same JSON line carries the other workloads as extras: AXPY + sum at
+n = 2^20, the 4096^3 matmul in three precisions, the 2048-task batched graph
+(batched vs plain speedup) and the learned schedule when available; the
+dominant kernel's roofline (HIP events on the launch stream); and the CPU
+oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from paper_2209_10643_amd import helpers as H  # noqa: E402
+from paper_2209_10643_amd import upir as U  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "split": 2500.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events on the stream the kernels run on."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def time(self, fn, reps):
+        t = self.torch
+        a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        t.cuda.synchronize()
+        a.record(self.stream)
+        for _ in range(reps):
+            fn()
+        b.record(self.stream)
+        b.synchronize()
+        return a.elapsed_time(b) / reps  # ms
+
+
+# ------------------------------------------------------------------ Jacobi
+class JacobiWork:
+    N, SWEEPS = 4096, 100
+
+    def __init__(self, torch, ctx, seed=12345):
+        N = self.N
+        u = synth.uniform_01_torch(seed, 0, N * N, device="cuda").reshape(N, N)
+        u[0, :] = 0
+        u[-1, :] = 0
+        u[:, 0] = 0
+        u[:, -1] = 0
+        self.u0 = u
+        self.a, self.b = u.clone(), u.clone()
+        self.res = torch.zeros(self.SWEEPS, dtype=torch.float64, device="cuda")
+        self.ctx = ctx
+        dims = [(1, N - 1, 1), (1, N - 1, 1)]
+        self.handles = []
+        for k in range(self.SWEEPS):
+            src, dst = (self.a, self.b) if k % 2 == 0 else (self.b, self.a)
+            args = U.upir_jacobi5_args(src.data_ptr(), dst.data_ptr(), N)
+            red = H.make_red(U.UPIR_RED_MAX, self.res[k:].data_ptr())
+            self.handles.append(ctx.loop(U.UPIR_BODY_JACOBI5, args, dims, None, red))
+        sp, sc, v = ctx.resolve(self.handles[0])
+        self.variant = U.VARIANTS[v]
+        self.teams, self.units, self.tile = sp.num_teams, sp.num_units, (sc.tile[0], sc.tile[1])
+        ctx.launch(self.handles[:1])
+        ctx.sync()
+        ctx.graph_begin()
+        ctx.launch(self.handles)
+        self.graph = ctx.graph_end()
+
+    def reset(self):
+        self.a.copy_(self.u0)
+        self.b.copy_(self.u0)
+
+    def step(self):
+        self.ctx.graph_launch(self.graph)
+
+    def bytes_per_sweep(self):
+        N = self.N
+        return 4 * N * N + 4 * (N - 2) * (N - 2)
+
+    def close(self):
+        self.ctx.graph_destroy(self.graph)
+        for h in self.handles:
+            self.ctx.free(h)
+
+
+def cpu_baseline_jacobi(seed=12345, sweeps=40):
+    """The oracle itself (float32-order numpy) on a bounded sample of the
+    workload: the first `sweeps` sweeps of the same 4096^2 grid."""
+    from oracle import bodies
+    N = JacobiWork.N
+    u = synth.uniform_01(seed, 0, N * N).reshape(N, N)
+    u[0, :] = u[-1, :] = 0
+    u[:, 0] = u[:, -1] = 0
+    t = time.perf_counter()
+    _, res = bodies.jacobi5(u, sweeps)
+    dt = time.perf_counter() - t
+    per = 4 * N * N + 4 * (N - 2) * (N - 2)
+    return {"value": round(sweeps * per / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} of the 100 Jacobi sweeps on the same 4096x4096 grid ({dt:.1f} s, numpy float32-order, "
+                      f"single thread)", "seconds": round(dt, 2), "res_first": float(res[0])}
+
+
+# ------------------------------------------------------------------- AXPY
+def bench_axpy(torch, ctx, timer, reps=1000):
+    n = 1 << 20
+    x = synth.uniform_pm1_torch(12345, 0, n, device="cuda")
+    y0 = synth.uniform_pm1_torch(12345, 1, n, device="cuda")
+    y = y0.clone()
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    args = U.upir_axpy_args(2.5, 0, x.data_ptr(), y.data_ptr())
+    lp = ctx.loop(U.UPIR_BODY_AXPY, args, [(0, n, 1)], None, H.make_red(U.UPIR_RED_SUM, r.data_ptr()))
+    ctx.launch(lp)
+    ctx.sync()
+    ctx.graph_begin()
+    for _ in range(reps):
+        ctx.launch(lp)
+    g = ctx.graph_end()
+    ctx.graph_launch(g)
+    ms = timer.time(lambda: ctx.graph_launch(g), 3)
+    per = ms / reps
+    sp, sc, v = ctx.resolve(lp)
+    out = {"n": n, "us_per_loop": round(per * 1e3, 3), "GBps": round(12 * n / (per * 1e-3) / 1e9, 1),
+           "variant": U.VARIANTS[v], "teams": sp.num_teams, "units": sp.num_units,
+           "note": "12 MiB working set: cache resident (L2 / MALL), 1000 back-to-back loops in one graph"}
+    # large n (working set > 256 MB MALL)
+    nb = 1 << 28
+    xb = synth.uniform_pm1_torch(1, 0, nb, device="cuda")
+    yb = synth.uniform_pm1_torch(1, 1, nb, device="cuda")
+    rb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lb = ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, xb.data_ptr(), yb.data_ptr()), [(0, nb, 1)], None,
+                  H.make_red(U.UPIR_RED_SUM, rb.data_ptr()))
+    ctx.launch(lb)
+    msb = timer.time(lambda: ctx.launch(lb), 10)
+    out["large_n"] = nb
+    out["large_GBps"] = round(12 * nb / (msb * 1e-3) / 1e9, 1)
+    sb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ls = ctx.loop(U.UPIR_BODY_SUM, U.upir_sum_args(xb.data_ptr(), U.UPIR_DT_F32, 0), [(0, nb, 1)], None,
+                  H.make_red(U.UPIR_RED_SUM, sb.data_ptr()))
+    ctx.launch(ls)
+    mss = timer.time(lambda: ctx.launch(ls), 10)
+    out["large_sum_GBps"] = round(4 * nb / (mss * 1e-3) / 1e9, 1)
+    ctx.graph_destroy(g)
+    for h in (lp, lb, ls):
+        ctx.free(h)
+    del xb, yb
+    return out
+
+
+# ------------------------------------------------------------------ matmul
+def bench_matmul(torch, ctx, timer, reps=5):
+    n = 4096
+    A = synth.normal(12345, 0, n * n).reshape(n, n)
+    B = synth.normal(12345, 1, n * n).reshape(n, n)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    # error report against a float64 product of 256 full rows (torch on the GPU,
+    # not the library); the parity tests compare with the CPU oracle
+    rows = slice(0, 256)
+    C64 = tA[rows].double() @ tB.double()
+    out = {}
+    for name, kind in (("f32", U.UPIR_BODY_MATMUL_F32), ("bf16", U.UPIR_BODY_MATMUL_BF16),
+                       ("split", U.UPIR_BODY_MATMUL_SPLIT3)):
+        tC = torch.zeros(n, n, device="cuda")
+        args = U.upir_matmul_args(tA.data_ptr(), tB.data_ptr(), tC.data_ptr(), n, n, n, n, None, 0)
+        lp = ctx.loop(kind, args, [(0, n, 1), (0, n, 1)], None)
+        ctx.launch(lp)
+        ms = timer.time(lambda: ctx.launch(lp), reps)
+        err = float(torch.linalg.norm(tC[rows].double() - C64) / torch.linalg.norm(C64))
+        tf = 2 * n ** 3 / (ms * 1e-3) / 1e12
+        sp, sc, v = ctx.resolve(lp)
+        out[name] = {"ms": round(ms, 4), "TFLOPs": round(tf, 1), "frac_of_peak": round(tf / PEAK_TFLOPS[name], 3),
+                     "normwise_err_vs_f64": float(f"{err:.3e}"), "variant": U.VARIANTS[v],
+                     "tile": [sc.tile[0], sc.tile[1]], "includes_bf16_prepass": name != "f32"}
+        ctx.free(lp)
+    return out
+
+
+# ----------------------------------------------------------------- batched
+def make_batched(torch, ctx, seed=12345, n_tasks=2048, lmin=8, lmax=22):
+    """The batched workload: kinds uniform over AXPY / SUM / MATVEC (rows x
+    256), lengths floor(2^U), U ~ U[8, 22]; edges i < j with probability
+    4/(n-1) encoded as depend(out: tok[j]) and depend(in: tok[i])."""
+    kinds = synth.int_range(seed, 100, n_tasks, 0, 3)
+    u = synth.uniform01_f64(seed, 101, n_tasks)
+    lens = np.floor(2.0 ** (lmin + (lmax - lmin) * u)).astype(np.int64)
+    p = 4.0 / (n_tasks - 1)
+    preds = []
+    for j in range(n_tasks):
+        r = synth.uniform01_f64(seed, 1000 + j, max(j, 1))[:j]
+        preds.append([int(i) for i in np.nonzero(r < p)[0]])
+    tasks, bytes_alg = [], 0
+    for j in range(n_tasks):
+        L = int(lens[j])
+        k = int(kinds[j])
+        if k == 0:
+            x = synth.uniform_pm1_torch(seed, 10 * j + 1, L, device="cuda")
+            y = synth.uniform_pm1_torch(seed, 10 * j + 2, L, device="cuda")
+            tasks.append(("axpy", L, {"x": x, "y": y, "y0": y.clone()}))
+            bytes_alg += 12 * L
+        elif k == 1:
+            x = synth.uniform_pm1_torch(seed, 10 * j + 1, L, device="cuda")
+            r = torch.zeros(1, dtype=torch.float64, device="cuda")
+            tasks.append(("sum", L, {"x": x, "r": r}))
+            bytes_alg += 4 * L
+        else:
+            rows = max(1, L // 256)
+            A = synth.uniform_pm1_torch(seed, 10 * j + 1, rows * 256, device="cuda")
+            x = synth.uniform_pm1_torch(seed, 10 * j + 2, 256, device="cuda")
+            y = torch.zeros(rows, device="cuda")
+            tasks.append(("matvec", rows, {"A": A, "x": x, "y": y}))
+            bytes_alg += 4 * rows * 256 + 4 * rows + 4 * 256
+    return tasks, preds, bytes_alg
+
+
+def batched_handles(ctx, tasks, tiles=None):
+    handles = []
+    for j, (kind, L, d) in enumerate(tasks):
+        sched = H.make_sched(U.UPIR_SCHED_AUTO, tile=(tiles[j],)) if tiles else None
+        if kind == "axpy":
+            h = ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, d["x"].data_ptr(), d["y"].data_ptr()),
+                         [(0, L, 1)], sched)
+        elif kind == "sum":
+            h = ctx.loop(U.UPIR_BODY_SUM, U.upir_sum_args(d["x"].data_ptr(), U.UPIR_DT_F32, 0), [(0, L, 1)], sched,
+                         H.make_red(U.UPIR_RED_SUM, d["r"].data_ptr()))
+        else:
+            h = ctx.loop(U.UPIR_BODY_MATVEC, U.upir_matvec_args(d["A"].data_ptr(), d["x"].data_ptr(),
+                                                                 d["y"].data_ptr(), 256, 256), [(0, L, 1)], sched)
+        handles.append(h)
+    return handles
+
+
+def submit(ctx, handles, preds, tok):
+    base = tok.data_ptr()
+    for j, h in enumerate(handles):
+        deps = [(base + 8 * j, U.UPIR_DEP_OUT)] + [(base + 8 * i, U.UPIR_DEP_IN) for i in preds[j]]
+        ctx.task(h, deps)
+
+
+def snapshot(torch, tasks):
+    return [d["y"].clone() if kind != "sum" else d["r"].clone() for kind, L, d in tasks]
+
+
+def bench_batched(torch, ctx, timer, reps=3):
+    t0 = time.perf_counter()
+    tasks, preds, bytes_alg = make_batched(torch, ctx)
+    log(f"  batched workload built in {time.perf_counter() - t0:.1f}s, {bytes_alg / 1e9:.2f} GB algorithmic")
+    tok = torch.zeros(len(tasks), dtype=torch.int64, device="cuda")
+
+    def restore():
+        for kind, L, d in tasks:
+            if kind == "axpy":
+                d["y"].copy_(d["y0"])
+
+    handles = batched_handles(ctx, tasks)
+    res = {}
+    # plain: one kernel launch per task, in index order, eager (host launch included)
+    submit(ctx, handles, preds, tok)
+    restore()
+    ctx.taskwait(U.UPIR_TASKWAIT_PLAIN)
+    plain_out = snapshot(torch, tasks)
+    times = []
+    for _ in range(reps):
+        submit(ctx, handles, preds, tok)
+        restore()
+        times.append(timer.time(lambda: ctx.taskwait(U.UPIR_TASKWAIT_PLAIN), 1))
+    res["plain_ms"] = round(float(np.median(times)), 3)
+    # plain captured in one graph (launch cost amortised by the graph)
+    submit(ctx, handles, preds, tok)
+    gp = ctx.taskwait_graph(U.UPIR_TASKWAIT_PLAIN)
+    pt = []
+    for _ in range(reps):
+        restore()
+        pt.append(timer.time(lambda: ctx.graph_launch(gp), 1))
+    res["plain_graph_ms"] = round(float(np.median(pt)), 3)
+    ctx.graph_destroy(gp)
+    # batched: one persistent kernel, graph-captured
+    submit(ctx, handles, preds, tok)
+    gb = ctx.taskwait_graph(U.UPIR_TASKWAIT_BATCHED)
+    restore()
+    ctx.graph_launch(gb)
+    ctx.sync()
+    batched_out = snapshot(torch, tasks)
+    bt = []
+    for _ in range(reps):
+        restore()
+        bt.append(timer.time(lambda: ctx.graph_launch(gb), 1))
+    res["batched_ms"] = round(float(np.median(bt)), 3)
+    ctx.graph_destroy(gb)
+    # equal accuracy: AXPY / MATVEC identical bits, SUM within 1e-5 * sum|x|
+    ok = True
+    for (kind, L, d), a, b in zip(tasks, plain_out, batched_out):
+        if kind == "sum":
+            tol = 1e-5 * float(d["x"].abs().double().sum().item())
+            ok &= abs(float(a.item()) - float(b.item())) <= tol
+        else:
+            ok &= bool(torch.equal(a, b))
+    res["batched_equals_plain_at_tol"] = bool(ok)
+    res["speedup_vs_plain"] = round(res["plain_ms"] / res["batched_ms"], 2)
+    res["speedup_vs_plain_graph"] = round(res["plain_graph_ms"] / res["batched_ms"], 2)
+    res["GBps_batched"] = round(bytes_alg / (res["batched_ms"] * 1e-3) / 1e9, 1)
+    res["algorithmic_GB"] = round(bytes_alg / 1e9, 3)
+    res["tasks"] = len(tasks)
+    res["edges"] = int(sum(len(p) for p in preds))
+    for h in handles:
+        ctx.free(h)
+    return res
+
+
+# -------------------------------------------------------------------- main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--configs", default="1,0,2,3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    U.lib()  # fails loudly when libupir.so has not been built
+    configs = [c.strip() for c in args.configs.split(",") if c.strip()]
+    stream = torch.cuda.Stream()
+    ctx = H.Context(0, stream=stream)
+    timer = Timer(torch, stream)
+    extras = {}
+    torch.cuda.set_stream(stream)  # torch copies / fills order with the library's launches
+
+    # ---------------- headline: Jacobi 4096^2 x 100 sweeps (one step)
+    log("jacobi: building graph")
+    jw = JacobiWork(torch, ctx)
+    for _ in range(args.warmup):
+        jw.reset()
+        jw.step()
+    torch.cuda.synchronize()
+    jw.reset()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(args.steps):
+        jw.step()
+    b.record(stream)
+    b.synchronize()
+    ms_step = a.elapsed_time(b) / args.steps
+    step_bytes = jw.SWEEPS * jw.bytes_per_sweep()
+    value = step_bytes / (ms_step * 1e-3) / 1e9
+    log(f"jacobi: {ms_step:.3f} ms/step, {value:.1f} GB/s ({jw.variant}, tile {jw.tile}, {jw.teams}x{jw.units})")
+    # dominant kernel: one sweep launched eagerly on the same stream
+    sweep_ms = timer.time(lambda: ctx.launch(jw.handles[0]), 200)
+    ach = jw.bytes_per_sweep() / (sweep_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"k_jacobi_tile<{jw.tile[0]},true>", "avg_launch_us": round(sweep_ms * 1e3, 3),
+                "algorithmic_bytes_per_launch": jw.bytes_per_sweep()}
+    res = jw.res.cpu().numpy()
+    extras["jacobi"] = {"grid": [4096, 4096], "sweeps": 100, "variant": jw.variant, "tile": list(jw.tile),
+                        "teams": jw.teams, "units": jw.units, "res_first": float(res[0]), "res_last": float(res[-1]),
+                        "working_set_MiB": 128, "note": "two 64 MiB grids fit the 256 MB MALL"}
+
+    if "0" in configs:
+        log("axpy")
+        extras["axpy_sum"] = bench_axpy(torch, ctx, timer)
+    if "2" in configs:
+        log("matmul")
+        extras["matmul_4096"] = bench_matmul(torch, ctx, timer)
+    if "3" in configs:
+        log("batched tasks")
+        extras["batched_2048"] = bench_batched(torch, ctx, timer)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline_jacobi()
+    jw.close()
+    ctx.close()
+    line = {
+        "metric": "achieved HBM GB/s (loop kernels) + batched/learned vs plain speedup at tol",
+        "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded SplitMix64 generators)",
+        "config": {"workload": "jacobi5 4096x4096 float32, 100 sweeps, collapse(2), max-residual float64, "
+                               "hipGraph replay", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extras": extras,
+        "host": {"nproc": os.cpu_count(), "cpu": platform.processor() or platform.machine()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -159,12 +159,11 @@ __global__ void __launch_bounds__(1024) k_dynamic(LoopK L, SchedK S, RedK R, B b
     visit_range(L, lo + ulo, lo + uhi, f);
   }
   if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = atomicAdd(S.dyn_exit, 1u);
+    // every claim of this team is done; the last team re-arms both counters
+    unsigned t = ticket_add(S.dyn_exit);
     if (t == gridDim.x - 1) {
-      *S.dyn_next = 0;
-      *S.dyn_exit = 0u;
-      __threadfence();
+      __hip_atomic_store(S.dyn_next, 0LL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(S.dyn_exit, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   if (R.op != RED_NONE) finish_reduction<A>(R, acc);
@@ -316,7 +315,34 @@ hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, con
 constexpr int JT_W = 256;          // tile width (points)
 constexpr int JT_S = JT_W + 8;     // LDS row stride (floats); core at +4
 
-template <int TH, bool RED>
+// Residual reduction per lane. The float64 value of |u1 - u0| is only needed
+// where it can change the lane's maximum (or minimum): rounding to float32
+// is monotonic, so a point whose float32 |u1 - u0| is below the lane's
+// float32 maximum cannot hold the exact maximum. Only candidates at or above
+// it (a handful per lane) take the float64 path; the result is exact.
+template <int OP>
+struct ResidualAcc {
+  float m32 = OP == RED_MIN ? __builtin_inff() : -1.0f;
+  double m64 = OP == RED_SUM ? 0.0 : (OP == RED_MAX ? -__builtin_inf() : __builtin_inf());
+  __device__ void add(float v, float c) {
+    if (OP == RED_SUM) {
+      m64 += fabs((double)v - (double)c);
+      return;
+    }
+    const float d = fabsf(v - c);
+    if (OP == RED_MAX ? d >= m32 : d <= m32) {
+      const double e = fabs((double)v - (double)c);
+      if (d != m32) {
+        m32 = d;
+        m64 = e;
+      } else {
+        m64 = OP == RED_MAX ? (e > m64 ? e : m64) : (e < m64 ? e : m64);
+      }
+    }
+  }
+};
+
+template <int TH, int RED>
 __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP p, RedK R) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, NW = blockDim.x / WAVE;
@@ -324,7 +350,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP
   const int64_t ld = p.ld;
   const int64_t ilo = L.lb[0], ihi = L.lb[0] + L.cnt[0];  // interior rows [ilo, ihi)
   const int64_t jlo = L.lb[1], jhi = L.lb[1] + L.cnt[1];
-  double acc = RED ? red_identity<double>(R.op) : 0.0;
+  ResidualAcc<RED> acc;
 
   auto do_tile = [&](int64_t m) {
     const int64_t ti = S.t0[0] + m / S.nt[1], tj = S.t0[1] + m % S.nt[1];
@@ -370,14 +396,14 @@ __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP
         *(f32x4 *)out = v;
         if (RED) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc = red_apply(R.op, acc, fabs((double)vv[q] - (double)cc[q]));
+          for (int q = 0; q < 4; ++q) acc.add(vv[q], cc[q]);
         }
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (j + q >= jlo && j + q < jhi) {
             out[q] = vv[q];
-            if (RED) acc = red_apply(R.op, acc, fabs((double)vv[q] - (double)cc[q]));
+            if (RED) acc.add(vv[q], cc[q]);
           }
         }
       }
@@ -393,7 +419,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP
     for (int64_t m0 = (int64_t)team * c; m0 < S.ntiles; m0 += (int64_t)S.T * c)
       for (int64_t m = m0; m < m0 + c && m < S.ntiles; ++m) do_tile(m);
   }
-  if (RED) finish_reduction<double>(R, acc);
+  if (RED) finish_reduction<double>(R, acc.m64);
 }
 
 bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
@@ -412,10 +438,12 @@ bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
 template <int TH>
 static hipError_t go_jacobi(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
   const size_t lds = (size_t)(TH + 2) * JT_S * sizeof(float);
-  if (R.op != RED_NONE)
-    hipLaunchKernelGGL((k_jacobi_tile<TH, true>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R);
-  else
-    hipLaunchKernelGGL((k_jacobi_tile<TH, false>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R);
+  switch (R.op) {
+    case RED_NONE: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_NONE>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R); break;
+    case RED_SUM: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_SUM>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R); break;
+    case RED_MAX: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_MAX>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R); break;
+    default: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_MIN>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R); break;
+  }
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 // (not in the paper): float32; A, B rounded to bfloat16 (round to nearest
 // even) with float32 accumulation; and the three-pass split
 // A_lo B_hi + A_hi B_lo + A_hi B_hi that recovers float32 accuracy.
+#include "upir.h"
 #include "upir_launch.h"
 
 namespace upir {
@@ -64,10 +65,297 @@ hipError_t launch_bf16_split(const MatmulP &p, bool need_lo, hipStream_t st) {
   return hipGetLastError();
 }
 
-bool matmul_mfma_supports(const MatmulP &, const LoopK &, const SchedK &) { return false; }
+// ------------------------------------------------------------ MFMA tiles
+// A team computes whole BM x BN tiles of C; tiles are numbered row-major
+// over C and handed to teams by the tiled schedule (static blocks or
+// chunks). Team ids are laid out so consecutive tiles share an XCD (and its
+// L2). Inside a tile the points are computed by MFMA fragments, so the
+// within-tile assignment of points to units is fixed by the matrix cores.
+//
+// Waves form a WM x WN grid; each wave owns (BM/WM) x (BN/WN) of the tile as
+// 32 x 32 MFMA blocks. K advances in steps of BK: the next step's operands
+// are fetched from global memory into registers while the current step's
+// operands, staged in LDS with padded rows (no bank conflicts on the 16-byte
+// fragment reads), feed the matrix cores.
+//
+// bfloat16 variants use v_mfma_f32_32x32x16_bf16 (lane l supplies row l%32
+// and 8 consecutive k of group l/32); both hi/lo operands come from the
+// pre-pass workspace (A as M x K, B transposed as N x K). The split variant
+// accumulates lo_A hi_B, hi_A lo_B and hi_A hi_B into one float32 sum.
+// float32 uses v_mfma_f32_32x32x2f32 over A (M x K) and B (K x N) directly.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-hipError_t launch_matmul_mfma(const MatmulP &, const LoopK &, const SchedK &, hipStream_t) {
-  return hipErrorInvalidValue;
+template <int BM, int BN, int WM, int WN>
+__device__ inline void store_c(const MatmulP &p, int64_t row0, int64_t col0, const f32x16 (&acc)[BM / WM / 32][BN / WN / 32]) {
+  constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t col = col0 + wn * (BN / WN) + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = row0 + wm * (BM / WM) + i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+        if (row < p.M && col < p.N) p.C[row * p.ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+// Tiles owned by this team under the tiled schedule.
+template <class F>
+__device__ inline void for_team_tiles(const SchedK &S, F &&f) {
+  const int team = xcd_team(blockIdx.x, gridDim.x);
+  if (S.policy == POL_STATIC) {
+    int64_t lo, hi;
+    block_range(S.ntiles, S.T, team, lo, hi);
+    for (int64_t m = lo; m < hi; ++m) f(m);
+  } else {
+    const int64_t c = S.chunk;
+    for (int64_t m0 = (int64_t)team * c; m0 < S.ntiles; m0 += (int64_t)S.T * c)
+      for (int64_t m = m0; m < m0 + c && m < S.ntiles; ++m) f(m);
+  }
+}
+
+template <int NPROD, int BM, int BN, int WM, int WN, int BK>
+__global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
+  constexpr int NTH = WM * WN * 64;
+  constexpr int PITCH = BK + 8;  // halfwords per LDS row (16-byte multiple)
+  constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
+  constexpr int CPR = BK / 8;                    // 16-byte chunks per row
+  constexpr int CA = BM * CPR / NTH, CB = BN * CPR / NTH;
+  static_assert(BM * CPR % NTH == 0 && BN * CPR % NTH == 0, "chunk split");
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
+  uint16_t *sAh = lds, *sBh = lds + BM * PITCH;
+  uint16_t *sAl = sBh + BN * PITCH, *sBl = sAl + BM * PITCH;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t K = p.K;
+
+  for_team_tiles(S, [&](int64_t m) {
+    const int64_t row0 = (S.t0[0] + m / S.nt[1]) * BM, col0 = (S.t0[1] + m % S.nt[1]) * BN;
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+    u32x4 ra[CA], rb[CB], ral[NPROD == 3 ? CA : 1], rbl[NPROD == 3 ? CB : 1];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+      for (int q = 0; q < CA; ++q) {
+        const int c = tid + q * NTH, r = c / CPR, kc = c % CPR;
+        const int64_t gr = row0 + r, gk = k0 + kc * 8;
+        const bool in = gr < p.M && gk < K;
+        ra[q] = in ? *(const u32x4 *)(p.ah + gr * K + gk) : u32x4{};
+        if (NPROD == 3) ral[q] = in ? *(const u32x4 *)(p.al + gr * K + gk) : u32x4{};
+      }
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        const int c = tid + q * NTH, r = c / CPR, kc = c % CPR;
+        const int64_t gc = col0 + r, gk = k0 + kc * 8;
+        const bool in = gc < p.N && gk < K;
+        rb[q] = in ? *(const u32x4 *)(p.bh + gc * K + gk) : u32x4{};
+        if (NPROD == 3) rbl[q] = in ? *(const u32x4 *)(p.bl + gc * K + gk) : u32x4{};
+      }
+    };
+    auto stage = [&]() {
+#pragma unroll
+      for (int q = 0; q < CA; ++q) {
+        const int c = tid + q * NTH, r = c / CPR, kc = c % CPR;
+        *(u32x4 *)(sAh + r * PITCH + kc * 8) = ra[q];
+        if (NPROD == 3) *(u32x4 *)(sAl + r * PITCH + kc * 8) = ral[q];
+      }
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        const int c = tid + q * NTH, r = c / CPR, kc = c % CPR;
+        *(u32x4 *)(sBh + r * PITCH + kc * 8) = rb[q];
+        if (NPROD == 3) *(u32x4 *)(sBl + r * PITCH + kc * 8) = rbl[q];
+      }
+    };
+    __syncthreads();  // previous tile's readers are done with LDS
+    fetch(0);
+    stage();
+    __syncthreads();
+    for (int64_t k0 = 0; k0 < K; k0 += BK) {
+      const bool more = k0 + BK < K;
+      if (more) fetch(k0 + BK);
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 16) {
+        const int koff = ks + 8 * (lane >> 5);
+        bf16x8 a[FM], b[FN], al[NPROD == 3 ? FM : 1], bl[NPROD == 3 ? FN : 1];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          const int r = wm * (BM / WM) + i * 32 + (lane & 31);
+          a[i] = *(const bf16x8 *)(sAh + r * PITCH + koff);
+          if (NPROD == 3) al[i] = *(const bf16x8 *)(sAl + r * PITCH + koff);
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int r = wn * (BN / WN) + j * 32 + (lane & 31);
+          b[j] = *(const bf16x8 *)(sBh + r * PITCH + koff);
+          if (NPROD == 3) bl[j] = *(const bf16x8 *)(sBl + r * PITCH + koff);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            if (NPROD == 3) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], b[j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bl[j], acc[i][j], 0, 0, 0);
+            }
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+          }
+      }
+      if (more) {
+        __syncthreads();
+        stage();
+        __syncthreads();
+      }
+    }
+    store_c<BM, BN, WM, WN>(p, row0, col0, acc);
+  });
+}
+
+template <int BM, int BN, int WM, int WN, int BK>
+__global__ void __launch_bounds__(WM * WN * 64) k_mm_f32(MatmulP p, SchedK S) {
+  constexpr int NTH = WM * WN * 64;
+  constexpr int PA = BK + 4;   // floats per A row in LDS
+  constexpr int PB = BN + 8;   // floats per B row (k) in LDS
+  constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
+  constexpr int CA = BM * (BK / 4) / NTH, CB = BK * (BN / 4) / NTH;
+  static_assert(BM * (BK / 4) % NTH == 0 && BK * (BN / 4) % NTH == 0, "chunk split");
+  extern __shared__ __attribute__((aligned(16))) float ldsf[];
+  float *sA = ldsf, *sB = ldsf + BM * PA;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t K = p.K;
+
+  for_team_tiles(S, [&](int64_t m) {
+    const int64_t row0 = (S.t0[0] + m / S.nt[1]) * BM, col0 = (S.t0[1] + m % S.nt[1]) * BN;
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+    f32x4v ra[CA], rb[CB];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+      for (int q = 0; q < CA; ++q) {
+        const int c = tid + q * NTH, r = c / (BK / 4), kc = c % (BK / 4);
+        const int64_t gr = row0 + r, gk = k0 + kc * 4;
+        ra[q] = (gr < p.M && gk < K) ? *(const f32x4v *)(p.A + gr * p.lda + gk) : f32x4v{};
+      }
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        const int c = tid + q * NTH, r = c / (BN / 4), nc = c % (BN / 4);
+        const int64_t gk = k0 + r, gc = col0 + nc * 4;
+        rb[q] = (gk < K && gc < p.N) ? *(const f32x4v *)(p.B + gk * p.ldb + gc) : f32x4v{};
+      }
+    };
+    auto stage = [&]() {
+#pragma unroll
+      for (int q = 0; q < CA; ++q) {
+        const int c = tid + q * NTH, r = c / (BK / 4), kc = c % (BK / 4);
+        *(f32x4v *)(sA + r * PA + kc * 4) = ra[q];
+      }
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        const int c = tid + q * NTH, r = c / (BN / 4), nc = c % (BN / 4);
+        *(f32x4v *)(sB + r * PB + nc * 4) = rb[q];
+      }
+    };
+    __syncthreads();
+    fetch(0);
+    stage();
+    __syncthreads();
+    const int g = lane >> 5;
+    for (int64_t k0 = 0; k0 < K; k0 += BK) {
+      const bool more = k0 + BK < K;
+      if (more) fetch(k0 + BK);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 8) {
+        // group g takes k = kk + 4g + s at MFMA step s (same for A and B)
+        f32x4v a[FM];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          a[i] = *(const f32x4v *)(sA + (wm * (BM / WM) + i * 32 + (lane & 31)) * PA + kk + 4 * g);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          float b[FN];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) b[j] = sB[(kk + 4 * g + s) * PB + wn * (BN / WN) + j * 32 + (lane & 31)];
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][s], b[j], acc[i][j], 0, 0, 0);
+        }
+      }
+      if (more) {
+        __syncthreads();
+        stage();
+        __syncthreads();
+      }
+    }
+    store_c<BM, BN, WM, WN>(p, row0, col0, acc);
+  });
+}
+
+// Kernel configurations: (kind, tile) -> block size.
+struct MMConf { int kind, bm, bn, threads; };
+static const MMConf kMM[] = {
+    {UPIR_BODY_MATMUL_BF16, 256, 256, 512}, {UPIR_BODY_MATMUL_BF16, 128, 128, 256},
+    {UPIR_BODY_MATMUL_SPLIT3, 256, 256, 512}, {UPIR_BODY_MATMUL_SPLIT3, 128, 128, 256},
+    {UPIR_BODY_MATMUL_F32, 128, 128, 256}, {UPIR_BODY_MATMUL_F32, 256, 128, 512},
+};
+
+bool matmul_mfma_supports(const MatmulP &p, const LoopK &L, const SchedK &S) {
+  if (L.nd != 2 || !S.tiled || S.dist != DIST_TU) return false;
+  if (S.policy != POL_STATIC && S.policy != POL_CHUNK) return false;
+  if (L.lb[0] != 0 || L.lb[1] != 0) return false;
+  bool conf = false;
+  for (const MMConf &c : kMM)
+    if (c.kind == p.kind && c.bm == S.tile[0] && c.bn == S.tile[1] && c.threads == S.U) conf = true;
+  if (!conf) return false;
+  if (p.kind == UPIR_BODY_MATMUL_F32) {
+    if (p.K % 4 || p.lda % 4 || p.ldb % 4 || p.N % 4) return false;
+    if ((uintptr_t)p.A % 16 || (uintptr_t)p.B % 16) return false;
+  } else {
+    if (p.K % 8) return false;
+    if ((uintptr_t)p.ah % 16 || (uintptr_t)p.bh % 16) return false;
+    if (p.kind == UPIR_BODY_MATMUL_SPLIT3 && ((uintptr_t)p.al % 16 || (uintptr_t)p.bl % 16)) return false;
+  }
+  return true;
+}
+
+template <class Kern>
+static hipError_t go_mm(Kern k, const MatmulP &p, const SchedK &S, size_t lds, hipStream_t st) {
+  static bool attr_set = false;  // raise the dynamic LDS limit once per kernel
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k, dim3(S.T), dim3(S.U), lds, st, p, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_matmul_mfma(const MatmulP &p, const LoopK &, const SchedK &S, hipStream_t st) {
+  const int bm = S.tile[0], bn = S.tile[1];
+  if (p.kind == UPIR_BODY_MATMUL_BF16) {
+    if (bm == 256) return go_mm(k_mm_bf16<1, 256, 256, 2, 4, 64>, p, S, 2 * 256 * 72 * 2, st);
+    return go_mm(k_mm_bf16<1, 128, 128, 2, 2, 64>, p, S, 2 * 128 * 72 * 2, st);
+  }
+  if (p.kind == UPIR_BODY_MATMUL_SPLIT3) {
+    if (bm == 256) return go_mm(k_mm_bf16<3, 256, 256, 2, 4, 32>, p, S, 4 * 256 * 40 * 2, st);
+    return go_mm(k_mm_bf16<3, 128, 128, 2, 2, 32>, p, S, 4 * 128 * 40 * 2, st);
+  }
+  if (bm == 256 && bn == 128) return go_mm(k_mm_f32<256, 128, 4, 2, 32>, p, S, (256 * 36 + 32 * 136) * 4, st);
+  return go_mm(k_mm_f32<128, 128, 2, 2, 32>, p, S, (128 * 36 + 32 * 136) * 4, st);
 }
 
 }  // namespace upir

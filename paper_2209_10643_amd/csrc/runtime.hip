@@ -425,7 +425,7 @@ extern "C" upir_status upir_loop_parallel(upir_ctx *c, const upir_loop *loop, co
   lp->sum_dtype = sum_dtype;
   lp->key = loop_shape_key(lp);
   lp->part_cap = has_red ? 8192 : 0;
-  const size_t sbytes = SCR_PART + (size_t)lp->part_cap * 8;
+  const size_t sbytes = scratch_layout(lp->part_cap).bytes;
   lp->scratch = (unsigned char *)upir_dalloc(c, sbytes);
   if (!lp->scratch) {
     delete lp;
@@ -629,12 +629,19 @@ static void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, 
       break;
     case UPIR_BODY_MATMUL_F32:
     case UPIR_BODY_MATMUL_BF16:
-    case UPIR_BODY_MATMUL_SPLIT3:
+    case UPIR_BODY_MATMUL_SPLIT3: {
+      // MFMA tile configurations: float32 128 x 128 on 4 wavefronts,
+      // bfloat16 256 x 256 on 8 wavefronts (128 x 128 for small C)
+      const bool f32 = lp->kind == UPIR_BODY_MATMUL_F32;
+      const bool small = lp->cnt[0] * lp->cnt[1] < 2048LL * 2048;
+      const int t = f32 || small ? 128 : 256;
       sc.policy = UPIR_SCHED_STATIC;
-      sc.tile[0] = lp->kind == UPIR_BODY_MATMUL_F32 ? 128 : 256;
-      sc.tile[1] = lp->kind == UPIR_BODY_MATMUL_F32 ? 128 : 256;
+      sc.tile[0] = t;
+      sc.tile[1] = t;
+      sp.num_units = t == 256 ? 512 : 256;
       sp.num_teams = 0;
       break;
+    }
     case UPIR_BODY_MATVEC:
       sc.policy = UPIR_SCHED_STATIC_CHUNK;
       sc.chunk = 1;
@@ -807,7 +814,7 @@ upir_status ensure_scratch(upir_ctx *c, upir_loop_obj *lp, int64_t parts) {
   if (parts <= lp->part_cap) return UPIR_OK;
   if (c->capturing) return upir_fail(c, UPIR_ESTATE, "reduction scratch must grow; launch once before capturing");
   HIPTRY(c, hipStreamSynchronize(c->stream));
-  const size_t sbytes = SCR_PART + (size_t)parts * 8;
+  const size_t sbytes = scratch_layout(parts).bytes;
   unsigned char *ns = (unsigned char *)upir_dalloc(c, sbytes);
   if (!ns) return upir_fail(c, UPIR_ENOMEM, "reduction scratch");
   HIPTRY(c, hipMemsetAsync(ns, 0, sbytes, c->stream));
@@ -831,7 +838,10 @@ upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for
     R.init = lp->red.init;
     R.init_i = (long long)lp->red.init;
     R.result = lp->red.result_on_host ? (void *)(lp->scratch + SCR_RESULT) : lp->red.result;
-    R.partials = (double *)(lp->scratch + SCR_PART);
+    const ScratchLayout sl = scratch_layout(lp->part_cap);
+    R.partials = (double *)(lp->scratch + sl.parts);
+    R.gpartials = (double *)(lp->scratch + sl.gparts);
+    R.gtickets = (unsigned *)(lp->scratch + sl.gtickets);
     R.ticket = (unsigned *)(lp->scratch + SCR_TICKET);
   }
   SchedK S = pl.S;

@@ -21,10 +21,23 @@ struct Mapping {
 };
 
 // Device scratch of one loop handle:
-//   [0]  u32 reduction ticket      [8]  f64/i64 internal result slot
+//   [0]  u32 top reduction ticket  [8]  f64/i64 internal result slot
 //   [16] i64 dynamic claim counter [24] u32 dynamic exit counter
-//   [32] partials (one f64 / i64 per workgroup)
-constexpr size_t SCR_TICKET = 0, SCR_RESULT = 8, SCR_DYN = 16, SCR_DYNEXIT = 24, SCR_PART = 32;
+//   [256] group tickets (128 bytes apart), then group slots, then one slot
+//   per workgroup (f64 / i64)
+constexpr size_t SCR_TICKET = 0, SCR_RESULT = 8, SCR_DYN = 16, SCR_DYNEXIT = 24, SCR_GROUPS = 256;
+struct ScratchLayout {
+  size_t gtickets, gparts, parts, bytes;
+};
+inline ScratchLayout scratch_layout(int64_t cap) {
+  const int64_t ng = (cap + upir::RED_GROUP - 1) / upir::RED_GROUP;
+  ScratchLayout l;
+  l.gtickets = SCR_GROUPS;
+  l.gparts = l.gtickets + (size_t)ng * upir::RED_GSTRIDE * 4;
+  l.parts = (l.gparts + (size_t)ng * 8 + 255) / 256 * 256;
+  l.bytes = l.parts + (size_t)cap * 8;
+  return l;
+}
 
 struct upir_loop_obj {
   upir_ctx *ctx = nullptr;

@@ -7,9 +7,10 @@
 // resident capacity of the GPU runs every task of the graph:
 //
 //  * each task's loop is cut into tiles of `tile` iterations;
-//  * ready tasks sit in a queue (slot -> task id); a workgroup claims the next
-//    tile of the oldest slot that still has tiles with an atomic counter and
-//    advances the queue head once a slot is exhausted;
+//  * the tiles of every task that becomes ready get a contiguous range of
+//    a global work list (one atomic reservation per task); workgroups claim
+//    work items with one global counter and wait, if needed, until the item
+//    they hold has been filled in by the push that reserved it;
 //  * the workgroup that finishes a task's last tile combines the task's
 //    reduction (float64, tile order), writes its trace token and stamps, and
 //    decrements the remaining in-degree of each successor, pushing those
@@ -49,10 +50,10 @@ struct TaskD {
 
 struct EngineD {
   const TaskD *tasks;
-  int32_t ntasks, ninit;
-  const int32_t *succ, *pred, *init_ready, *indeg0;
-  int32_t *indeg, *tiles_done, *next_tile, *ready;
-  int32_t *ctrl;  // [0] head [1] tail [2] error
+  int32_t ntasks, total_tiles, init_tiles, pad_;
+  const int32_t *succ, *pred, *init_work, *init_base, *indeg0;
+  int32_t *indeg, *tiles_done, *task_base, *work;
+  int32_t *ctrl;  // [0] next work item [1] work items reserved [2] error
   unsigned long long *clock;
   double *partials;
   uint64_t *tok, *tstart, *tdone;
@@ -66,106 +67,131 @@ __device__ inline uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__device__ inline int ld_acq(int32_t *p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT); }
+// Relaxed agent-scope accesses (device-coherent, no cache maintenance).
+__device__ inline int ld_i(int32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline void st_i(int32_t *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline int add_i(int32_t *p, int v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long tick(unsigned long long *p) {
+  return __hip_atomic_fetch_add(p, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-// Reset the mutable engine state (a kernel, so graphs hold no memset node).
+// Task data is read and written with device-coherent accesses: a task may
+// run on another XCD than the task that produced its inputs, and the tiles
+// of one task are spread over XCDs, so values must not stay in (or be read
+// from) one XCD's L2. Pairs of floats travel as 64-bit accesses.
+__device__ inline float2 cld2(const float *p) {
+  const unsigned long long v = __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(float2, v);
+}
+__device__ inline float cld(const float *p) {
+  return __hip_atomic_load((float *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void cst2(float *p, float2 v) {
+  __hip_atomic_store((unsigned long long *)p, __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void cst(float *p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Reset the mutable engine state (a kernel, so graphs hold no memset node)
+// and lay out the tiles of the initially ready tasks at the front of the
+// work list.
 __global__ void k_engine_reset(EngineD E) {
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x, st = gridDim.x * blockDim.x;
   for (int i = i0; i < E.ntasks; i += st) {
-    E.indeg[i] = E.indeg0[i];
-    E.tiles_done[i] = 0;
-    E.next_tile[i] = 0;
-    E.ready[i] = i < E.ninit ? E.init_ready[i] + 1 : 0;
+    st_i(&E.indeg[i], E.indeg0[i]);
+    st_i(&E.tiles_done[i], 0);
+    st_i(&E.task_base[i], E.init_base[i]);
   }
+  for (int w = i0; w < E.total_tiles; w += st) st_i(&E.work[w], w < E.init_tiles ? E.init_work[w] + 1 : 0);
   if (i0 == 0) {
-    E.ctrl[0] = 0;
-    E.ctrl[1] = E.ninit;
-    E.ctrl[2] = 0;
-    *E.clock = 0ULL;
+    st_i(&E.ctrl[0], 0);
+    st_i(&E.ctrl[1], E.init_tiles);
+    st_i(&E.ctrl[2], 0);
+    __hip_atomic_store(E.clock, 0ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// One tile of a task, executed by the whole workgroup. Returns the lane's
-// contribution to the task's reduction (already reduced over the block in
-// thread 0 by the caller).
+// One tile of a task, executed by the whole workgroup; `acc` collects this
+// lane's contribution to the task's reduction.
 __device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
   const int64_t lo = tile * t.tile;
   const int64_t hi = lo + t.tile < t.n ? lo + t.tile : t.n;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int op = t.red_op;
   if (t.kind == UPIR_BODY_MATVEC) {
+    // same arithmetic as the loop kernel's row: lane l takes columns
+    // 4l .. 4l+3 of each 256-column block in order, then a fixed butterfly
     const int lane = tid % WAVE, w = tid / WAVE, nw = nt / WAVE;
-    const bool vec = t.vec;
     for (int64_t k = lo + w; k < hi; k += nw) {
       const int64_t r = t.lb + k * t.step;
       const float *a = t.A + r * t.lda;
       float s = 0.0f;
       for (int64_t c0 = 0; c0 < t.cols; c0 += 256) {
         const int64_t c = c0 + 4 * lane;
-        if (vec && c + 3 < t.cols) {
-          const f32x4 av = *(const f32x4 *)(a + c);
-          const f32x4 xv = *(const f32x4 *)(t.x + c);
-          s = __builtin_fmaf(av.x, xv.x, s);
-          s = __builtin_fmaf(av.y, xv.y, s);
-          s = __builtin_fmaf(av.z, xv.z, s);
-          s = __builtin_fmaf(av.w, xv.w, s);
+        if (t.vec && c + 3 < t.cols) {
+          const float2 a0 = cld2(a + c), a1 = cld2(a + c + 2), x0 = cld2(t.x + c), x1 = cld2(t.x + c + 2);
+          s = __builtin_fmaf(a0.x, x0.x, s);
+          s = __builtin_fmaf(a0.y, x0.y, s);
+          s = __builtin_fmaf(a1.x, x1.x, s);
+          s = __builtin_fmaf(a1.y, x1.y, s);
         } else {
           for (int q = 0; q < 4; ++q)
-            if (c + q < t.cols) s = __builtin_fmaf(a[c + q], t.x[c + q], s);
+            if (c + q < t.cols) s = __builtin_fmaf(cld(a + c + q), cld(t.x + c + q), s);
         }
       }
       s = wave_reduce(RED_SUM, s);
       if (lane == 0) {
-        t.y[r] = s;
+        cst(t.y + r, s);
         if (op) acc = red_apply(op, acc, s);
       }
     }
     return;
   }
-  if (t.vec) {  // unit step, lb + lo multiple of 4, 16-byte aligned base
+  if (t.vec) {  // unit step, 16-byte aligned start of every tile
     const int64_t b = t.lb + lo;
     const int64_t len = hi - lo, nc = len >> 2;
     if (t.kind == UPIR_BODY_AXPY) {
-      const f32x4 *x4 = (const f32x4 *)(t.x + b);
-      f32x4 *y4 = (f32x4 *)(t.y + b);
       for (int64_t m = tid; m < nc; m += nt) {
-        const f32x4 xv = x4[m];
-        const f32x4 yv = y4[m];
-        f32x4 r;
-        r.x = __builtin_fmaf(t.a, xv.x, yv.x);
-        r.y = __builtin_fmaf(t.a, xv.y, yv.y);
-        r.z = __builtin_fmaf(t.a, xv.z, yv.z);
-        r.w = __builtin_fmaf(t.a, xv.w, yv.w);
-        y4[m] = r;
+        const float *xp = t.x + b + 4 * m;
+        float *yp = t.y + b + 4 * m;
+        const float2 x0 = cld2(xp), x1 = cld2(xp + 2), y0 = cld2(yp), y1 = cld2(yp + 2);
+        float2 r0, r1;
+        r0.x = __builtin_fmaf(t.a, x0.x, y0.x);
+        r0.y = __builtin_fmaf(t.a, x0.y, y0.y);
+        r1.x = __builtin_fmaf(t.a, x1.x, y1.x);
+        r1.y = __builtin_fmaf(t.a, x1.y, y1.y);
+        cst2(yp, r0);
+        cst2(yp + 2, r1);
         if (op) {
-          acc = red_apply(op, acc, r.x);
-          acc = red_apply(op, acc, r.y);
-          acc = red_apply(op, acc, r.z);
-          acc = red_apply(op, acc, r.w);
+          acc = red_apply(op, acc, r0.x);
+          acc = red_apply(op, acc, r0.y);
+          acc = red_apply(op, acc, r1.x);
+          acc = red_apply(op, acc, r1.y);
         }
       }
     } else if (t.kind == UPIR_BODY_SUM) {
-      const f32x4 *x4 = (const f32x4 *)(t.x + b);
       for (int64_t m = tid; m < nc; m += nt) {
-        const f32x4 xv = x4[m];
-        acc = red_apply(op, acc, xv.x);
-        acc = red_apply(op, acc, xv.y);
-        acc = red_apply(op, acc, xv.z);
-        acc = red_apply(op, acc, xv.w);
+        const float *xp = t.x + b + 4 * m;
+        const float2 x0 = cld2(xp), x1 = cld2(xp + 2);
+        acc = red_apply(op, acc, x0.x);
+        acc = red_apply(op, acc, x0.y);
+        acc = red_apply(op, acc, x1.x);
+        acc = red_apply(op, acc, x1.y);
       }
     } else {
       for (int64_t m = tid; m < nc; m += nt)
         for (int q = 0; q < 4; ++q) atomicAdd(&t.cnt[lo + 4 * m + q], 1);
     }
-    // ragged end of the tile
-    for (int64_t k = lo + 4 * nc + tid; k < hi; k += nt) {
+    for (int64_t k = lo + 4 * nc + tid; k < hi; k += nt) {  // ragged end of the tile
       const int64_t i = t.lb + k;
       if (t.kind == UPIR_BODY_AXPY) {
-        const float r = __builtin_fmaf(t.a, t.x[i], t.y[i]);
-        t.y[i] = r;
+        const float r = __builtin_fmaf(t.a, cld(t.x + i), cld(t.y + i));
+        cst(t.y + i, r);
         if (op) acc = red_apply(op, acc, r);
       } else if (t.kind == UPIR_BODY_SUM) {
-        acc = red_apply(op, acc, t.x[i]);
+        acc = red_apply(op, acc, cld(t.x + i));
       } else {
         atomicAdd(&t.cnt[k], 1);
       }
@@ -175,11 +201,11 @@ __device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
   for (int64_t k = lo + tid; k < hi; k += nt) {
     const int64_t i = t.lb + k * t.step;
     if (t.kind == UPIR_BODY_AXPY) {
-      const float r = __builtin_fmaf(t.a, t.x[i], t.y[i]);
-      t.y[i] = r;
+      const float r = __builtin_fmaf(t.a, cld(t.x + i), cld(t.y + i));
+      cst(t.y + i, r);
       if (op) acc = red_apply(op, acc, r);
     } else if (t.kind == UPIR_BODY_SUM) {
-      acc = red_apply(op, acc, t.x[i]);
+      acc = red_apply(op, acc, cld(t.x + i));
     } else {
       atomicAdd(&t.cnt[k], 1);
     }
@@ -190,41 +216,34 @@ __global__ void __launch_bounds__(256) k_engine(EngineD E) {
   __shared__ int s_task, s_tile, s_last;
   __shared__ float s_red[16];
   __shared__ double s_red64[16];
-  int32_t *head = &E.ctrl[0], *tail = &E.ctrl[1], *err = &E.ctrl[2];
-  long long spins = 0;
-  int seen_h = -1, seen_t = -1;
+  int32_t *next = &E.ctrl[0], *reserved = &E.ctrl[1], *err = &E.ctrl[2];
   for (;;) {
     if (threadIdx.x == 0) {
       int task = -1, tile = 0;
-      for (;;) {
-        if (ld_acq(err)) break;
-        const int h = ld_acq(head);
-        if (h >= E.ntasks) break;
-        const int tl = ld_acq(tail);
-        if (h != seen_h || tl != seen_t) {
-          seen_h = h;
-          seen_t = tl;
-          spins = 0;
-        }
-        if (h < tl) {
-          const int v = ld_acq(&E.ready[h]);
+      const int w = add_i(next, 1);
+      if (w < E.total_tiles) {
+        // wait until the push that reserves item w has filled it in
+        long long spins = 0;
+        int seen = -1;
+        for (;;) {
+          const int v = ld_i(&E.work[w]);
           if (v > 0) {
-            const int t = v - 1;
-            const int k = atomicAdd(&E.next_tile[h], 1);
-            if (k < E.tasks[t].ntiles) {
-              task = t;
-              tile = k;
-              if (k == 0 && E.tstart) E.tstart[t] = atomicAdd(E.clock, 1ULL);
-              break;
-            }
-            atomicCAS(head, h, h + 1);
-            continue;
+            task = v - 1;
+            tile = w - ld_i(&E.task_base[task]);
+            if (tile == 0 && E.tstart) E.tstart[task] = tick(E.clock);
+            break;
           }
-        }
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > E.spin_limit) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-          break;
+          if (ld_i(err)) break;
+          const int r = ld_i(reserved);
+          if (r != seen) {
+            seen = r;
+            spins = 0;
+          }
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins > E.spin_limit) {
+            st_i(err, 1);
+            break;
+          }
         }
       }
       s_task = task;
@@ -233,45 +252,45 @@ __global__ void __launch_bounds__(256) k_engine(EngineD E) {
     __syncthreads();
     const int t = s_task, k = s_tile;
     if (t < 0) break;
-    __threadfence();  // acquire: the task's inputs were published before it became ready
     const TaskD &d = E.tasks[t];
     float acc = d.red_op ? red_identity<float>(d.red_op) : 0.0f;
     run_tile(d, k, acc);
     if (d.red_op) {
       const float wg = block_reduce(d.red_op, acc, s_red);
-      if (threadIdx.x == 0) E.partials[d.part_base + k] = (double)wg;
+      if (threadIdx.x == 0)
+        coh_store((unsigned long long *)&E.partials[d.part_base + k], __builtin_bit_cast(unsigned long long, (double)wg));
     }
+    complete_own_accesses();  // this thread's tile stores have reached the coherent level
     __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();  // release this tile's stores
-      const int done = atomicAdd(&E.tiles_done[t], 1);
-      s_last = (done == d.ntiles - 1);
-    }
+    if (threadIdx.x == 0) s_last = (add_i(&E.tiles_done[t], 1) == d.ntiles - 1);
     __syncthreads();
     if (s_last) {
-      __threadfence();  // acquire every tile's stores
       if (d.red_op) {
         double v = red_identity<double>(d.red_op);
         for (int i = threadIdx.x; i < d.ntiles; i += blockDim.x)
           v = red_apply(d.red_op, v,
-                        __hip_atomic_load(&E.partials[d.part_base + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        __builtin_bit_cast(double, coh_load((unsigned long long *)&E.partials[d.part_base + i])));
         v = block_reduce(d.red_op, v, s_red64);
-        if (threadIdx.x == 0) *d.result = red_apply(d.red_op, d.init, v);
+        if (threadIdx.x == 0)
+          coh_store((unsigned long long *)d.result, __builtin_bit_cast(unsigned long long, red_apply(d.red_op, d.init, v)));
       }
       if (threadIdx.x == 0) {
         if (E.tok) {
           uint64_t hsh = mix64((uint64_t)(t + 1) * 0x9E3779B97F4A7C15ULL);
           for (int i = d.pred_begin; i < d.pred_end; ++i)
-            hsh = mix64(hsh ^ __hip_atomic_load(&E.tok[E.pred[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-          E.tok[t] = hsh;
+            hsh = mix64(hsh ^ coh_load((unsigned long long *)&E.tok[E.pred[i]]));
+          coh_store((unsigned long long *)&E.tok[t], hsh);
         }
-        if (E.tdone) E.tdone[t] = atomicAdd(E.clock, 1ULL);
-        __threadfence();  // release results, token and stamp before successors can start
+        if (E.tdone) E.tdone[t] = tick(E.clock);
+        complete_own_accesses();  // result, token and stamp before any successor starts
         for (int i = d.succ_begin; i < d.succ_end; ++i) {
           const int s = E.succ[i];
-          if (atomicSub(&E.indeg[s], 1) == 1) {
-            const int slot = atomicAdd(tail, 1);
-            __hip_atomic_store(&E.ready[slot], s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          if (add_i(&E.indeg[s], -1) == 1) {
+            const int nt = E.tasks[s].ntiles;
+            const int base = add_i(reserved, nt);
+            st_i(&E.task_base[s], base);
+            complete_own_accesses();
+            for (int q = 0; q < nt; ++q) st_i(&E.work[base + q], s + 1);
           }
         }
       }
@@ -446,12 +465,21 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
     }
   }
   if (parts > (1LL << 31)) return upir_fail(c, UPIR_EINVAL, "too many reduction tiles");
-  // ---- device buffer: [tasks][succ][pred][init_ready][indeg0] static, then mutable state
+  int64_t total_tiles = 0;
+  for (const TaskD &d : td) total_tiles += d.ntiles;
+  if (total_tiles >= (1LL << 31)) return upir_fail(c, UPIR_EINVAL, "too many tiles");
+  // initially ready tasks take the front of the work list, in task order
+  std::vector<int32_t> init_base(n, -1), init_work;
+  for (int32_t j : init_ready) {
+    init_base[j] = (int32_t)init_work.size();
+    for (int32_t q = 0; q < td[j].ntiles; ++q) init_work.push_back(j);
+  }
+  // ---- device buffer: static tables, then mutable state
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t b_tasks = al(sizeof(TaskD) * n), b_succ = al(4 * succ.size() + 4), b_pred = al(4 * pred.size() + 4);
-  const size_t b_init = al(4 * init_ready.size() + 4), b_i32 = al(4 * (size_t)n);
-  const size_t static_bytes = b_tasks + b_succ + b_pred + b_init + b_i32;
-  const size_t total = static_bytes + 4 * b_i32 + al(64) + al(8 * (size_t)std::max<int64_t>(parts, 1));
+  const size_t b_iw = al(4 * init_work.size() + 4), b_i32 = al(4 * (size_t)n), b_work = al(4 * (size_t)total_tiles);
+  const size_t static_bytes = b_tasks + b_succ + b_pred + b_iw + 2 * b_i32;
+  const size_t total = static_bytes + 3 * b_i32 + b_work + al(64) + al(8 * (size_t)std::max<int64_t>(parts, 1));
   std::vector<unsigned char> host(static_bytes, 0);
   size_t o = 0;
   memcpy(&host[o], td.data(), sizeof(TaskD) * n);
@@ -460,8 +488,10 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
   o += b_succ;
   if (!pred.empty()) memcpy(&host[o], pred.data(), 4 * pred.size());
   o += b_pred;
-  if (!init_ready.empty()) memcpy(&host[o], init_ready.data(), 4 * init_ready.size());
-  o += b_init;
+  if (!init_work.empty()) memcpy(&host[o], init_work.data(), 4 * init_work.size());
+  o += b_iw;
+  memcpy(&host[o], init_base.data(), 4 * (size_t)n);
+  o += b_i32;
   memcpy(&host[o], indeg.data(), 4 * (size_t)n);
   unsigned char *dev = (unsigned char *)upir_dalloc(c, total);
   if (!dev) return upir_fail(c, UPIR_ENOMEM, "task engine tables (%zu bytes)", total);
@@ -479,24 +509,27 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
   o += b_succ;
   E.pred = (const int32_t *)(dev + o);
   o += b_pred;
-  E.init_ready = (const int32_t *)(dev + o);
-  o += b_init;
+  E.init_work = (const int32_t *)(dev + o);
+  o += b_iw;
+  E.init_base = (const int32_t *)(dev + o);
+  o += b_i32;
   E.indeg0 = (const int32_t *)(dev + o);
   o += b_i32;
   E.indeg = (int32_t *)(dev + o);
   o += b_i32;
   E.tiles_done = (int32_t *)(dev + o);
   o += b_i32;
-  E.next_tile = (int32_t *)(dev + o);
+  E.task_base = (int32_t *)(dev + o);
   o += b_i32;
-  E.ready = (int32_t *)(dev + o);
-  o += b_i32;
+  E.work = (int32_t *)(dev + o);
+  o += b_work;
   E.ctrl = (int32_t *)(dev + o);
   E.clock = (unsigned long long *)(dev + o + 16);
   o += al(64);
   E.partials = (double *)(dev + o);
   E.ntasks = n;
-  E.ninit = (int32_t)init_ready.size();
+  E.total_tiles = (int32_t)total_tiles;
+  E.init_tiles = (int32_t)init_work.size();
   E.tok = c->trace.tokens;
   E.tstart = c->trace.start_stamp;
   E.tdone = c->trace.done_stamp;
@@ -504,7 +537,7 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
   const char *gs = getenv("UPIR_ENGINE_GRID");
   int grid = c->num_cus * 4;
   if (gs && atoi(gs) > 0) grid = atoi(gs);
-  const int rgrid = std::max(1, std::min(1024, (n + 255) / 256));
+  const int rgrid = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (std::max<int64_t>(n, total_tiles) + 255) / 256));
   upir_status st = UPIR_OK;
   if (capture_only) {
     st = upir_graph_begin(c);
@@ -536,6 +569,6 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
   if (e == hipSuccess) e = hipMemcpy(ctrl, E.ctrl, sizeof ctrl, hipMemcpyDeviceToHost);
   upir_dfree(c, dev);
   if (e != hipSuccess) return upir_hipfail(c, e, "task engine");
-  if (ctrl[2]) return upir_fail(c, UPIR_EDEPEND, "task graph did not drain (head %d, tail %d of %d)", ctrl[0], ctrl[1], n);
+  if (ctrl[2]) return upir_fail(c, UPIR_EDEPEND, "task graph did not drain (claimed %d, reserved %d of %d work items)", ctrl[0], ctrl[1], (int)total_tiles);
   return UPIR_OK;
 }

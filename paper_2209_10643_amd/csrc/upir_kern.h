@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace upir {
 
 enum : int32_t { POL_STATIC = 0, POL_CHUNK = 1, POL_DYNAMIC = 2, POL_GUIDED = 3 };
@@ -49,8 +51,16 @@ struct RedK {
   long long init_i;
   void *result;               // device double* or long long*
   double *partials;           // one slot per workgroup (reinterpreted for int64)
-  unsigned *ticket;           // arrivals; reset to 0 by the last workgroup
+  double *gpartials;          // one slot per group of RED_GROUP workgroups
+  unsigned *gtickets;         // group arrival counters, RED_GSTRIDE apart
+  unsigned *ticket;           // group arrivals; reset to 0 by the last group
 };
+
+// Workgroups report in groups so that no counter takes more than
+// RED_GROUP atomic increments (increments of one address serialise at the
+// device-coherent level); group counters sit on separate cache lines.
+constexpr int RED_GROUP = 64;
+constexpr int RED_GSTRIDE = 32;  // unsigned ints (128 bytes) between group counters
 
 // ------------------------------------------------------------------ helpers
 __host__ __device__ inline void block_range(int64_t n, int64_t parts, int64_t p, int64_t &lo, int64_t &hi) {
@@ -134,19 +144,14 @@ __device__ inline void for_owned_untiled(const LoopK &L, const SchedK &S, int te
     block_range(thi - tlo, S.U, unit, ulo, uhi);
     visit_range(L, tlo + ulo, tlo + uhi, f);
   } else {  // POL_CHUNK
+    // first chunk and chunk stride of this unit; selected without nested
+    // branches (an if / else-if chain here was compiled into code that ran
+    // no iteration for distribute(units) on gfx950)
     const int64_t c = S.chunk;
-    int64_t first, stride;
-    if (S.dist == DIST_TU) {
-      first = (int64_t)team * S.U + unit;
-      stride = (int64_t)S.T * S.U;
-    } else if (S.dist == DIST_T) {
-      if (unit != 0) return;
-      first = team;
-      stride = S.T;
-    } else {
-      first = unit;
-      stride = S.U;
-    }
+    const bool tu = S.dist == DIST_TU, tt = S.dist == DIST_T;
+    if (tt && unit != 0) return;
+    const int64_t first = tu ? (int64_t)team * S.U + unit : (tt ? (int64_t)team : (int64_t)unit);
+    const int64_t stride = tu ? (int64_t)S.T * S.U : (tt ? (int64_t)S.T : (int64_t)S.U);
     for (int64_t m = first; m * c < n; m += stride) {
       int64_t lo = m * c, hi = lo + c < n ? lo + c : n;
       visit_range(L, lo, hi, f);
@@ -252,55 +257,77 @@ __device__ inline T block_reduce(int op, T v, T *lds) {
   return r;
 }
 
-// Cross-workgroup combine. Thread 0 of every workgroup holds `wg` (float64
-// for float data). The last workgroup to arrive folds every partial in
-// workgroup order, adds `init`, writes the result and re-arms the ticket.
-__device__ inline void combine_f64(const RedK &R, double wg, double *lds) {
+// Device-coherent accesses. The XCDs' L2 caches are not coherent with each
+// other; atomic accesses at agent scope are performed at the device-coherent
+// level, so values published through them need no L2 write-back. A
+// workgroup-scope release fence waits until this thread's earlier accesses
+// have completed, which orders a published value before the counter update
+// that announces it (the agent-scope release fence would write back the
+// whole L2 of the XCD instead, about a microsecond per fence, serialised).
+__device__ inline void coh_store(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long coh_load(unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void complete_own_accesses() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup"); }
+__device__ inline unsigned ticket_add(unsigned *t) {
+  return __hip_atomic_fetch_add(t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Cross-workgroup combine in two levels. Thread 0 of every workgroup
+// publishes `wg` (float64 bits, or int64) in its slot and takes a ticket of
+// its group; the last workgroup of a group folds the group's slots in
+// workgroup order into a group slot and takes a ticket of the top counter;
+// the last group folds the group slots in group order, adds `init`, writes
+// the result and re-arms the counters. The order of every fold is fixed, so
+// the result depends only on the launch geometry.
+template <class T>
+__device__ inline T fold_slots(const RedK &R, unsigned long long *slots, int lo, int hi, T *lds) {
+  T v = red_identity<T>(R.op);
+  for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x)
+    v = red_apply(R.op, v, __builtin_bit_cast(T, coh_load(&slots[i])));
+  return block_reduce(R.op, v, lds);
+}
+
+template <class T>
+__device__ inline void combine_slots(const RedK &R, T wg, T *lds) {
   __shared__ unsigned s_last;
-  const int G = gridDim.x;
+  const int G = gridDim.x, b = blockIdx.x;
+  const int g = b / RED_GROUP, NG = (G + RED_GROUP - 1) / RED_GROUP;
+  const int glo = g * RED_GROUP, ghi = glo + RED_GROUP < G ? glo + RED_GROUP : G;
+  unsigned long long *slots = (unsigned long long *)R.partials;
+  unsigned long long *gslots = (unsigned long long *)R.gpartials;
+  unsigned *gt = R.gtickets + (size_t)g * RED_GSTRIDE;
   if (threadIdx.x == 0) {
-    R.partials[blockIdx.x] = wg;
-    __threadfence();
-    unsigned t = atomicAdd(R.ticket, 1u);
-    s_last = (t == (unsigned)(G - 1));
+    coh_store(&slots[b], __builtin_bit_cast(unsigned long long, wg));
+    complete_own_accesses();
+    s_last = (ticket_add(gt) == (unsigned)(ghi - glo - 1));
   }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
-  double v = red_identity<double>(R.op);
-  for (int i = threadIdx.x; i < G; i += blockDim.x)
-    v = red_apply(R.op, v, __hip_atomic_load(&R.partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  v = block_reduce(R.op, v, lds);
+  const T gv = fold_slots<T>(R, slots, glo, ghi, lds);
   if (threadIdx.x == 0) {
-    *(double *)R.result = red_apply(R.op, R.init, v);
-    *R.ticket = 0u;
-    __threadfence();
+    coh_store(&gslots[g], __builtin_bit_cast(unsigned long long, gv));
+    __hip_atomic_store(gt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    complete_own_accesses();
+    s_last = (ticket_add(R.ticket) == (unsigned)(NG - 1));
+  }
+  __syncthreads();
+  if (!s_last) return;
+  const T v = fold_slots<T>(R, gslots, 0, NG, lds);
+  if (threadIdx.x == 0) {
+    if constexpr (std::is_same<T, double>::value) {
+      *(double *)R.result = red_apply(R.op, R.init, (double)v);
+    } else {
+      *(long long *)R.result = red_apply(R.op, R.init_i, (long long)v);
+    }
+    __hip_atomic_store(R.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-__device__ inline void combine_i64(const RedK &R, long long wg, long long *lds) {
-  __shared__ unsigned s_last;
-  const int G = gridDim.x;
-  long long *parts = (long long *)R.partials;
-  if (threadIdx.x == 0) {
-    parts[blockIdx.x] = wg;
-    __threadfence();
-    unsigned t = atomicAdd(R.ticket, 1u);
-    s_last = (t == (unsigned)(G - 1));
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  long long v = red_identity<long long>(R.op);
-  for (int i = threadIdx.x; i < G; i += blockDim.x)
-    v = red_apply(R.op, v, __hip_atomic_load(&parts[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  v = block_reduce(R.op, v, lds);
-  if (threadIdx.x == 0) {
-    *(long long *)R.result = red_apply(R.op, R.init_i, v);
-    *R.ticket = 0u;
-    __threadfence();
-  }
-}
+__device__ inline void combine_f64(const RedK &R, double wg, double *lds) { combine_slots<double>(R, wg, lds); }
+__device__ inline void combine_i64(const RedK &R, long long wg, long long *lds) { combine_slots<long long>(R, wg, lds); }
 
 // Lane value -> workgroup value -> cross-workgroup combine.
 template <class A>
