@@ -65,8 +65,9 @@ class Timer:
 class JacobiWork:
     N, SWEEPS = 4096, 100
 
-    def __init__(self, torch, ctx, seed=12345):
+    def __init__(self, torch, ctx, seed=12345, tune=True):
         N = self.N
+        self.tuned_us = None
         u = synth.uniform_01_torch(seed, 0, N * N, device="cuda").reshape(N, N)
         u[0, :] = 0
         u[-1, :] = 0
@@ -83,6 +84,10 @@ class JacobiWork:
             args = U.upir_jacobi5_args(src.data_ptr(), dst.data_ptr(), N)
             red = H.make_red(U.UPIR_RED_MAX, self.res[k:].data_ptr())
             self.handles.append(ctx.loop(U.UPIR_BODY_JACOBI5, args, dims, None, red))
+        if tune:  # schedule(auto): the exhaustive tuner picks tile, units and teams
+            best_us = C.c_double()
+            U.upir_tune(ctx.h, None, self.handles[0], 5, None, None, C.byref(best_us))
+            self.tuned_us = best_us.value
         sp, sc, v = ctx.resolve(self.handles[0])
         self.variant = U.VARIANTS[v]
         self.teams, self.units, self.tile = sp.num_teams, sp.num_units, (sc.tile[0], sc.tile[1])
@@ -331,13 +336,157 @@ def bench_batched(torch, ctx, timer, reps=3):
     return res
 
 
+# --------------------------------------------------------- learned schedule
+class LoopPool:
+    """Device buffers that the schedule-learning loops point into."""
+
+    def __init__(self, torch, max_elems=1 << 24, grid=4096):
+        self.x = synth.uniform_pm1_torch(7, 0, max_elems, device="cuda")
+        self.y = synth.uniform_pm1_torch(7, 1, max_elems, device="cuda")
+        self.cnt = torch.zeros(max_elems, dtype=torch.int32, device="cuda")
+        self.g0 = synth.uniform_01_torch(7, 2, grid * grid, device="cuda")
+        self.g1 = self.g0.clone()
+        self.r = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.max_elems, self.grid = max_elems, grid
+
+
+def make_loop(ctx, pool, kind, size, red):
+    """One loop of a given kind and size on the pool's buffers."""
+    P = pool
+    if kind == "axpy":
+        args = U.upir_axpy_args(2.5, 0, P.x.data_ptr(), P.y.data_ptr())
+        return ctx.loop(U.UPIR_BODY_AXPY, args, [(0, size, 1)], None,
+                        H.make_red(U.UPIR_RED_SUM, P.r.data_ptr()) if red else None)
+    if kind == "sum":
+        args = U.upir_sum_args(P.x.data_ptr(), U.UPIR_DT_F32, 0)
+        return ctx.loop(U.UPIR_BODY_SUM, args, [(0, size, 1)], None, H.make_red(U.UPIR_RED_SUM, P.r.data_ptr()))
+    if kind == "cover":
+        return ctx.loop(U.UPIR_BODY_COVER, U.upir_cover_args(P.cnt.data_ptr()), [(0, size, 1)], None)
+    if kind == "matvec":
+        args = U.upir_matvec_args(P.x.data_ptr(), P.y.data_ptr(), P.y[P.max_elems // 2:].data_ptr(), 256, 256)
+        return ctx.loop(U.UPIR_BODY_MATVEC, args, [(0, size, 1)], None,
+                        H.make_red(U.UPIR_RED_SUM, P.r.data_ptr()) if red else None)
+    if kind == "jacobi":
+        args = U.upir_jacobi5_args(P.g0.data_ptr(), P.g1.data_ptr(), size)
+        return ctx.loop(U.UPIR_BODY_JACOBI5, args, [(1, size - 1, 1), (1, size - 1, 1)], None,
+                        H.make_red(U.UPIR_RED_MAX, P.r.data_ptr()))
+    raise ValueError(kind)
+
+
+def learning_loops(n_random=500, seed=12345, n_tasks=2048):
+    """The loop population: the batched workload's 2048 loops, the AXPY and
+    Jacobi configurations, and `n_random` loops of random kind and
+    log-uniform size."""
+    loops = []
+    kinds = synth.int_range(seed, 100, n_tasks, 0, 3)
+    u = synth.uniform01_f64(seed, 101, n_tasks)
+    lens = np.floor(2.0 ** (8 + 14 * u)).astype(np.int64)
+    for j in range(n_tasks):
+        k = ("axpy", "sum", "matvec")[int(kinds[j])]
+        L = int(lens[j])
+        loops.append((k, max(1, L // 256) if k == "matvec" else L, k == "sum"))
+    loops.append(("axpy", 1 << 20, True))
+    loops.append(("jacobi", 4096, True))
+    rk = synth.int_range(seed, 200, n_random, 0, 5)
+    ru = synth.uniform01_f64(seed, 201, n_random)
+    rr = synth.int_range(seed, 202, n_random, 0, 2)
+    for i in range(n_random):
+        k = ("axpy", "sum", "cover", "matvec", "jacobi")[int(rk[i])]
+        if k == "matvec":
+            size = int(2.0 ** (4 + 12 * ru[i]))
+        elif k == "jacobi":
+            size = int(2.0 ** (5 + 7 * ru[i]))
+        else:
+            size = int(2.0 ** (8 + 16 * ru[i]))
+        loops.append((k, size, bool(rr[i]) or k == "sum"))
+    return loops
+
+
+def db_rows(ctx):
+    n = C.c_int64()
+    U.upir_tune_db_size(ctx.h, C.byref(n))
+    feats = np.zeros((n.value, 32), np.float32)
+    t = np.zeros(n.value, np.float32)
+    keys = np.zeros(n.value, np.int64)
+    f = (C.c_float * 32)()
+    lt, kk = C.c_float(), C.c_int64()
+    for i in range(n.value):
+        U.upir_tune_db_row(ctx.h, i, f, C.byref(lt), C.byref(kk))
+        feats[i] = np.frombuffer(f, np.float32)
+        t[i], keys[i] = lt.value, kk.value
+    return feats, t, keys
+
+
+def model_predict(torch, ctx, feats):
+    X = torch.from_numpy(np.ascontiguousarray(feats)).cuda()
+    Y = torch.zeros(len(feats), device="cuda")
+    U.upir_model_forward(ctx.h, X.data_ptr(), len(feats), Y.data_ptr())
+    ctx.sync()
+    return Y.cpu().numpy()
+
+
+def learned_schedule(torch, ctx, n_random=500, reps=3, epochs=150, batch=256, lr=1e-3, seed=12345, log_every=500):
+    """Tune every loop exhaustively (the timing table), train the cost model
+    on the GPU with 20% of the loops held out, then compare on the held-out
+    loops the measured time of the model's choice with the library default
+    (candidate 0) and with the tuner's best."""
+    pool = LoopPool(torch)
+    loops = learning_loops(n_random, seed)
+    spans = []  # (first row, candidates, loop key) per loop
+    t0 = time.perf_counter()
+    for i, (k, size, red) in enumerate(loops):
+        h = make_loop(ctx, pool, k, size, red)
+        n0 = C.c_int64()
+        U.upir_tune_db_size(ctx.h, C.byref(n0))
+        U.upir_tune(ctx.h, None, h, reps, None, None, None)
+        n1 = C.c_int64()
+        U.upir_tune_db_size(ctx.h, C.byref(n1))
+        spans.append((n0.value, n1.value - n0.value))
+        ctx.free(h)
+        if log_every and (i + 1) % log_every == 0:
+            log(f"  tuned {i + 1}/{len(loops)} loops, {n1.value} rows, {time.perf_counter() - t0:.1f}s")
+    tune_s = time.perf_counter() - t0
+    feats, t, keys = db_rows(ctx)
+    U.upir_model_init(ctx.h, seed)
+    tr, ho = C.c_float(), C.c_float()
+    t1 = time.perf_counter()
+    U.upir_model_train(ctx.h, 0, batch, lr, 0, C.byref(tr), C.byref(ho))
+    mse0 = (tr.value, ho.value)
+    U.upir_model_train(ctx.h, epochs, batch, lr, 0, C.byref(tr), C.byref(ho))
+    train_s = time.perf_counter() - t1
+    pred = model_predict(torch, ctx, feats)
+    held = [(a, b) for (a, b), kk in zip(spans, (keys[a] for a, _ in spans)) if kk % 5 == 0 and b > 0]
+    ratio_def, regret = [], []
+    for a, b in held:
+        tt = 2.0 ** t[a:a + b].astype(np.float64)
+        pick = int(np.argmin(pred[a:a + b]))
+        ratio_def.append(tt[0] / tt[pick])
+        regret.append(tt[pick] / tt.min())
+    gm = lambda v: float(np.exp(np.mean(np.log(v)))) if len(v) else float("nan")
+    # the batched workload's loops launched one by one: default vs learned
+    nb = 2048
+    plain_def = sum(2.0 ** t[a] for a, b in spans[:nb])
+    plain_learn = sum(2.0 ** t[a + int(np.argmin(pred[a:a + b]))] for a, b in spans[:nb])
+    plain_best = sum(float(np.min(2.0 ** t[a:a + b])) for a, b in spans[:nb])
+    return {
+        "loops": len(loops), "rows": int(len(t)), "tune_s": round(tune_s, 1), "train_s": round(train_s, 2),
+        "epochs": epochs, "batch": batch, "mse_initial_train_holdout": [round(mse0[0], 4), round(mse0[1], 4)],
+        "mse_final_train_holdout": [round(tr.value, 4), round(ho.value, 4)],
+        "holdout_loops": len(held),
+        "holdout_gain_vs_default_geomean": round(gm(ratio_def), 4),
+        "holdout_regret_vs_tuner_geomean": round(gm(regret), 4),
+        "batched_loops_kernel_us_default": round(plain_def, 1), "batched_loops_kernel_us_learned": round(plain_learn, 1),
+        "batched_loops_kernel_us_tuner": round(plain_best, 1),
+    }
+
+
 # -------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--configs", default="1,0,2,3")
+    ap.add_argument("--configs", default="1,0,2,3,4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -380,10 +529,11 @@ def main():
     ach = jw.bytes_per_sweep() / (sweep_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"k_jacobi_tile<{jw.tile[0]},true>", "avg_launch_us": round(sweep_ms * 1e3, 3),
+                "kernel": f"k_jacobi_tile<{jw.tile[0]},RED_MAX> ({jw.units} units)", "avg_launch_us": round(sweep_ms * 1e3, 3),
                 "algorithmic_bytes_per_launch": jw.bytes_per_sweep()}
     res = jw.res.cpu().numpy()
     extras["jacobi"] = {"grid": [4096, 4096], "sweeps": 100, "variant": jw.variant, "tile": list(jw.tile),
+                        "schedule": "auto (exhaustive tuner)", "tuned_sweep_us": jw.tuned_us,
                         "teams": jw.teams, "units": jw.units, "res_first": float(res[0]), "res_last": float(res[-1]),
                         "working_set_MiB": 128, "note": "two 64 MiB grids fit the 256 MB MALL"}
 
@@ -396,6 +546,9 @@ def main():
     if "3" in configs:
         log("batched tasks")
         extras["batched_2048"] = bench_batched(torch, ctx, timer)
+    if "4" in configs:
+        log("learned schedule: tuning, training, held-out evaluation")
+        extras["learned_schedule"] = learned_schedule(torch, ctx)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -425,17 +425,16 @@ extern "C" upir_status upir_loop_parallel(upir_ctx *c, const upir_loop *loop, co
   lp->sum_dtype = sum_dtype;
   lp->key = loop_shape_key(lp);
   lp->part_cap = has_red ? 8192 : 0;
-  const size_t sbytes = scratch_layout(lp->part_cap).bytes;
-  lp->scratch = (unsigned char *)upir_dalloc(c, sbytes);
+  lp->scratch = (unsigned char *)upir_dalloc(c, scratch_bytes(lp->part_cap));
   if (!lp->scratch) {
     delete lp;
     return upir_fail(c, UPIR_ENOMEM, "reduction scratch");
   }
   if (!c->none) {
-    hipError_t e = hipMemsetAsync(lp->scratch, 0, sbytes, c->stream);
-    if (e != hipSuccess) {
+    upir_status cs = clear_scratch(c, lp, lp->scratch, lp->part_cap);
+    if (cs) {
       free_loop(c, lp);
-      return upir_hipfail(c, e, "scratch clear");
+      return cs;
     }
   }
   if ((kind == UPIR_BODY_MATMUL_BF16 || kind == UPIR_BODY_MATMUL_SPLIT3) &&
@@ -602,7 +601,7 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Library default schedule and geometry for a body (used by AUTO when the
 // tuner and the model have nothing to say, and to fill num_teams = 0).
-static void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc) {
+void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc) {
   const int64_t n = lp->n;
   const int64_t cap = 8LL * c->num_cus;
   sc = upir_sched{};
@@ -810,14 +809,28 @@ upir_status resolve_plan(upir_ctx *c, const upir_spmd *spmd_in, upir_loop_obj *l
   return UPIR_OK;
 }
 
+bool red_is_int(const upir_loop_obj *lp) {
+  return lp->kind == UPIR_BODY_SUM && (lp->sum_dtype == UPIR_DT_I32 || lp->sum_dtype == UPIR_DT_I64);
+}
+
+// Header zero; reduction slots empty (float: all-ones pattern, int: flag 0).
+upir_status clear_scratch(upir_ctx *c, upir_loop_obj *lp, unsigned char *scr, int64_t cap) {
+  HIPTRY(c, hipMemsetAsync(scr, 0, SCR_SLOTS, c->stream));
+  if (cap > 0) HIPTRY(c, hipMemsetAsync(scr + SCR_SLOTS, red_is_int(lp) ? 0 : 0xFF, (size_t)cap * 16, c->stream));
+  return UPIR_OK;
+}
+
 upir_status ensure_scratch(upir_ctx *c, upir_loop_obj *lp, int64_t parts) {
   if (parts <= lp->part_cap) return UPIR_OK;
   if (c->capturing) return upir_fail(c, UPIR_ESTATE, "reduction scratch must grow; launch once before capturing");
   HIPTRY(c, hipStreamSynchronize(c->stream));
-  const size_t sbytes = scratch_layout(parts).bytes;
-  unsigned char *ns = (unsigned char *)upir_dalloc(c, sbytes);
+  unsigned char *ns = (unsigned char *)upir_dalloc(c, scratch_bytes(parts));
   if (!ns) return upir_fail(c, UPIR_ENOMEM, "reduction scratch");
-  HIPTRY(c, hipMemsetAsync(ns, 0, sbytes, c->stream));
+  upir_status st = clear_scratch(c, lp, ns, parts);
+  if (st) {
+    upir_dfree(c, ns);
+    return st;
+  }
   upir_dfree(c, lp->scratch);
   lp->scratch = ns;
   lp->part_cap = parts;
@@ -834,15 +847,12 @@ upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for
     st = ensure_scratch(c, lp, pl.S.T);
     if (st) return st;
     R.op = lp->red.op;
-    R.is_int = (lp->kind == UPIR_BODY_SUM && (lp->sum_dtype == UPIR_DT_I32 || lp->sum_dtype == UPIR_DT_I64));
+    R.is_int = red_is_int(lp);
     R.init = lp->red.init;
     R.init_i = (long long)lp->red.init;
     R.result = lp->red.result_on_host ? (void *)(lp->scratch + SCR_RESULT) : lp->red.result;
-    const ScratchLayout sl = scratch_layout(lp->part_cap);
-    R.partials = (double *)(lp->scratch + sl.parts);
-    R.gpartials = (double *)(lp->scratch + sl.gparts);
-    R.gtickets = (unsigned *)(lp->scratch + sl.gtickets);
-    R.ticket = (unsigned *)(lp->scratch + SCR_TICKET);
+    R.slots = (unsigned long long *)(lp->scratch + SCR_SLOTS);
+    R.spin_limit = 1LL << 22;
   }
   SchedK S = pl.S;
   S.dyn_next = (long long *)(lp->scratch + SCR_DYN);
@@ -865,7 +875,6 @@ upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for
         if (p.kind != UPIR_BODY_MATMUL_F32) e = launch_bf16_split(p, p.kind == UPIR_BODY_MATMUL_SPLIT3, c->stream);
         if (e != hipSuccess) break;
       }
-      if (lp->kind == UPIR_BODY_SUM && !R.is_int && lp->sum_dtype == UPIR_DT_I32) R.is_int = 1;
       e = launch_generic(lp->kind, pay, pl.L, S, R, c->stream);
     }
   }

@@ -21,23 +21,11 @@ struct Mapping {
 };
 
 // Device scratch of one loop handle:
-//   [0]  u32 top reduction ticket  [8]  f64/i64 internal result slot
+//   [0]  (unused)                  [8]  f64/i64 internal result slot
 //   [16] i64 dynamic claim counter [24] u32 dynamic exit counter
-//   [256] group tickets (128 bytes apart), then group slots, then one slot
-//   per workgroup (f64 / i64)
-constexpr size_t SCR_TICKET = 0, SCR_RESULT = 8, SCR_DYN = 16, SCR_DYNEXIT = 24, SCR_GROUPS = 256;
-struct ScratchLayout {
-  size_t gtickets, gparts, parts, bytes;
-};
-inline ScratchLayout scratch_layout(int64_t cap) {
-  const int64_t ng = (cap + upir::RED_GROUP - 1) / upir::RED_GROUP;
-  ScratchLayout l;
-  l.gtickets = SCR_GROUPS;
-  l.gparts = l.gtickets + (size_t)ng * upir::RED_GSTRIDE * 4;
-  l.parts = (l.gparts + (size_t)ng * 8 + 255) / 256 * 256;
-  l.bytes = l.parts + (size_t)cap * 8;
-  return l;
-}
+//   [256] reduction slots, 16 bytes per workgroup (value, flag)
+constexpr size_t SCR_RESULT = 8, SCR_DYN = 16, SCR_DYNEXIT = 24, SCR_SLOTS = 256;
+inline size_t scratch_bytes(int64_t cap) { return SCR_SLOTS + (size_t)cap * 16; }
 
 struct upir_loop_obj {
   upir_ctx *ctx = nullptr;
@@ -137,6 +125,8 @@ struct Plan {
 upir_status resolve_plan(upir_ctx *c, const upir_spmd *spmd, upir_loop_obj *lp, Plan &out);
 upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for_task);
 upir_status ensure_scratch(upir_ctx *c, upir_loop_obj *lp, int64_t parts);
+upir_status clear_scratch(upir_ctx *c, upir_loop_obj *lp, unsigned char *scr, int64_t cap);
+bool red_is_int(const upir_loop_obj *lp);
 upir_status resolve_payload(upir_ctx *c, upir_loop_obj *lp, unsigned char *payload);
 uint64_t loop_shape_key(const upir_loop_obj *lp);
 // candidate schedules for the tuner / model
@@ -145,4 +135,5 @@ bool candidate_at(upir_ctx *c, const upir_loop_obj *lp, int idx, upir_spmd &sp, 
 void candidate_features(upir_ctx *c, const upir_loop_obj *lp, const upir_spmd &sp, const upir_sched &sc,
                         float f[32]);
 bool model_pick(upir_ctx *c, upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc);
+void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc);
 }  // namespace upir

@@ -320,16 +320,9 @@ using namespace upir;
 
 static int64_t default_task_tile(int32_t kind) { return kind == UPIR_BODY_MATVEC ? 256 : 65536; }
 
-// tile size of a task: the schedule's tile[0] if given, else tuned / default
-static int64_t task_tile(upir_ctx *c, upir_loop_obj *lp) {
+// tile size of a task: the schedule's tile[0] if given, else the default
+static int64_t task_tile(upir_ctx *, upir_loop_obj *lp) {
   if (lp->sched.tile[0] > 0) return lp->sched.tile[0];
-  if (lp->sched.policy == UPIR_SCHED_AUTO) {
-    upir_spmd sp;
-    upir_sched sc;
-    auto it = c->tuned.find(lp->key ^ 0x7A5C0FFEEULL);
-    if (it != c->tuned.end() && it->second.sched.tile[0] > 0) return it->second.sched.tile[0];
-    if (c->model_on && model_pick(c, lp, sp, sc) && sc.tile[0] > 0) return sc.tile[0];
-  }
   return default_task_tile(lp->kind);
 }
 

@@ -50,17 +50,13 @@ struct RedK {
   double init;
   long long init_i;
   void *result;               // device double* or long long*
-  double *partials;           // one slot per workgroup (reinterpreted for int64)
-  double *gpartials;          // one slot per group of RED_GROUP workgroups
-  unsigned *gtickets;         // group arrival counters, RED_GSTRIDE apart
-  unsigned *ticket;           // group arrivals; reset to 0 by the last group
+  unsigned long long *slots;  // two words per workgroup: value, flag
+  long long spin_limit;       // bound on the combiner's wait per slot
 };
 
-// Workgroups report in groups so that no counter takes more than
-// RED_GROUP atomic increments (increments of one address serialise at the
-// device-coherent level); group counters sit on separate cache lines.
-constexpr int RED_GROUP = 64;
-constexpr int RED_GSTRIDE = 32;  // unsigned ints (128 bytes) between group counters
+// Empty float slot: all ones, a NaN that neither arithmetic nor a float32 to
+// float64 conversion produces. Integer slots carry a separate flag word.
+constexpr unsigned long long SLOT_EMPTY = ~0ULL;
 
 // ------------------------------------------------------------------ helpers
 __host__ __device__ inline void block_range(int64_t n, int64_t parts, int64_t p, int64_t &lo, int64_t &hi) {
@@ -275,54 +271,66 @@ __device__ inline unsigned ticket_add(unsigned *t) {
   return __hip_atomic_fetch_add(t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Cross-workgroup combine in two levels. Thread 0 of every workgroup
-// publishes `wg` (float64 bits, or int64) in its slot and takes a ticket of
-// its group; the last workgroup of a group folds the group's slots in
-// workgroup order into a group slot and takes a ticket of the top counter;
-// the last group folds the group slots in group order, adds `init`, writes
-// the result and re-arms the counters. The order of every fold is fixed, so
-// the result depends only on the launch geometry.
-template <class T>
-__device__ inline T fold_slots(const RedK &R, unsigned long long *slots, int lo, int hi, T *lds) {
-  T v = red_identity<T>(R.op);
-  for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x)
-    v = red_apply(R.op, v, __builtin_bit_cast(T, coh_load(&slots[i])));
-  return block_reduce(R.op, v, lds);
-}
-
+// Cross-workgroup combine. Every workgroup but the last one launched
+// publishes its value in its slot with one device-coherent store and
+// retires. The last workgroup (launched last, so the others are already
+// running or done) waits for every slot in turn, folds them in workgroup
+// order (each thread a fixed stride, then a fixed tree), adds `init`,
+// writes the result and empties the slots for the next launch. Integer
+// values are followed by a flag word, written after the value has
+// completed; float values mark their own slot, since an empty slot holds a
+// NaN pattern no float value takes. Waits are bounded (a NaN result reports
+// a slot that never arrived).
 template <class T>
 __device__ inline void combine_slots(const RedK &R, T wg, T *lds) {
-  __shared__ unsigned s_last;
+  constexpr bool INT = std::is_same<T, long long>::value;
   const int G = gridDim.x, b = blockIdx.x;
-  const int g = b / RED_GROUP, NG = (G + RED_GROUP - 1) / RED_GROUP;
-  const int glo = g * RED_GROUP, ghi = glo + RED_GROUP < G ? glo + RED_GROUP : G;
-  unsigned long long *slots = (unsigned long long *)R.partials;
-  unsigned long long *gslots = (unsigned long long *)R.gpartials;
-  unsigned *gt = R.gtickets + (size_t)g * RED_GSTRIDE;
-  if (threadIdx.x == 0) {
-    coh_store(&slots[b], __builtin_bit_cast(unsigned long long, wg));
-    complete_own_accesses();
-    s_last = (ticket_add(gt) == (unsigned)(ghi - glo - 1));
+  unsigned long long *sl = R.slots;
+  if (b != G - 1) {
+    if (threadIdx.x == 0) {
+      coh_store(&sl[2 * b], __builtin_bit_cast(unsigned long long, wg));
+      if (INT) {
+        complete_own_accesses();
+        coh_store(&sl[2 * b + 1], 1ULL);
+      }
+    }
+    return;
   }
+  __shared__ int s_missing;
+  if (threadIdx.x == 0) s_missing = 0;
   __syncthreads();
-  if (!s_last) return;
-  const T gv = fold_slots<T>(R, slots, glo, ghi, lds);
-  if (threadIdx.x == 0) {
-    coh_store(&gslots[g], __builtin_bit_cast(unsigned long long, gv));
-    __hip_atomic_store(gt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    complete_own_accesses();
-    s_last = (ticket_add(R.ticket) == (unsigned)(NG - 1));
+  T v = red_identity<T>(R.op);
+  for (int i = threadIdx.x; i < G - 1; i += blockDim.x) {
+    unsigned long long bits = 0;
+    long long spins = 0;
+    for (;;) {
+      if (INT) {
+        if (coh_load(&sl[2 * i + 1]) != 0ULL) {
+          bits = coh_load(&sl[2 * i]);
+          break;
+        }
+      } else {
+        bits = coh_load(&sl[2 * i]);
+        if (bits != SLOT_EMPTY) break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > R.spin_limit) {
+        s_missing = 1;
+        break;
+      }
+    }
+    v = red_apply(R.op, v, __builtin_bit_cast(T, bits));
+    coh_store(&sl[2 * i], INT ? 0ULL : SLOT_EMPTY);
+    if (INT) coh_store(&sl[2 * i + 1], 0ULL);
   }
-  __syncthreads();
-  if (!s_last) return;
-  const T v = fold_slots<T>(R, gslots, 0, NG, lds);
+  if (threadIdx.x == 0) v = red_apply(R.op, v, wg);  // this workgroup's own value, last
+  v = block_reduce(R.op, v, lds);
   if (threadIdx.x == 0) {
     if constexpr (std::is_same<T, double>::value) {
-      *(double *)R.result = red_apply(R.op, R.init, (double)v);
+      *(double *)R.result = s_missing ? __builtin_nan("") : red_apply(R.op, R.init, v);
     } else {
-      *(long long *)R.result = red_apply(R.op, R.init_i, (long long)v);
+      *(long long *)R.result = red_apply(R.op, R.init_i, v);
     }
-    __hip_atomic_store(R.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
