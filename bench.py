@@ -488,6 +488,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--configs", default="1,0,2,3,4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
@@ -505,6 +507,14 @@ def main():
     extras = {}
     torch.cuda.set_stream(stream)  # torch copies / fills order with the library's launches
 
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
     # ---------------- headline: Jacobi 4096^2 x 100 sweeps (one step)
     log("jacobi: building graph")
     jw = JacobiWork(torch, ctx)
@@ -568,7 +578,7 @@ def main():
         "extras": extras,
         "host": {"nproc": os.cpu_count(), "cpu": platform.processor() or platform.machine()},
     }
-    print(json.dumps(line), flush=True)
+    print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)), flush=True)
 
 
 if __name__ == "__main__":

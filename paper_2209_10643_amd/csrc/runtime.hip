@@ -816,7 +816,8 @@ bool red_is_int(const upir_loop_obj *lp) {
 // Header zero; reduction slots empty (float: all-ones pattern, int: flag 0).
 upir_status clear_scratch(upir_ctx *c, upir_loop_obj *lp, unsigned char *scr, int64_t cap) {
   HIPTRY(c, hipMemsetAsync(scr, 0, SCR_SLOTS, c->stream));
-  if (cap > 0) HIPTRY(c, hipMemsetAsync(scr + SCR_SLOTS, red_is_int(lp) ? 0 : 0xFF, (size_t)cap * 16, c->stream));
+  if (cap > 0)
+    HIPTRY(c, hipMemsetAsync(scr + SCR_SLOTS, red_is_int(lp) ? 0 : 0xFF, (size_t)cap * 8 * SLOT_WORDS, c->stream));
   return UPIR_OK;
 }
 

@@ -23,9 +23,9 @@ struct Mapping {
 // Device scratch of one loop handle:
 //   [0]  (unused)                  [8]  f64/i64 internal result slot
 //   [16] i64 dynamic claim counter [24] u32 dynamic exit counter
-//   [256] reduction slots, 16 bytes per workgroup (value, flag)
+//   [256] reduction slots, one 128-byte line per workgroup (value, flag)
 constexpr size_t SCR_RESULT = 8, SCR_DYN = 16, SCR_DYNEXIT = 24, SCR_SLOTS = 256;
-inline size_t scratch_bytes(int64_t cap) { return SCR_SLOTS + (size_t)cap * 16; }
+inline size_t scratch_bytes(int64_t cap) { return SCR_SLOTS + (size_t)cap * 8 * upir::SLOT_WORDS; }
 
 struct upir_loop_obj {
   upir_ctx *ctx = nullptr;

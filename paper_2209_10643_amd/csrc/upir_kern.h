@@ -56,7 +56,10 @@ struct RedK {
 
 // Empty float slot: all ones, a NaN that neither arithmetic nor a float32 to
 // float64 conversion produces. Integer slots carry a separate flag word.
+// Each workgroup's slot has a 128-byte cache line of its own: device-coherent
+// stores to one line from many workgroups are serialised.
 constexpr unsigned long long SLOT_EMPTY = ~0ULL;
+constexpr int SLOT_WORDS = 16;  // 64-bit words between slots
 
 // ------------------------------------------------------------------ helpers
 __host__ __device__ inline void block_range(int64_t n, int64_t parts, int64_t p, int64_t &lo, int64_t &hi) {
@@ -288,10 +291,10 @@ __device__ inline void combine_slots(const RedK &R, T wg, T *lds) {
   unsigned long long *sl = R.slots;
   if (b != G - 1) {
     if (threadIdx.x == 0) {
-      coh_store(&sl[2 * b], __builtin_bit_cast(unsigned long long, wg));
+      coh_store(&sl[SLOT_WORDS * b], __builtin_bit_cast(unsigned long long, wg));
       if (INT) {
         complete_own_accesses();
-        coh_store(&sl[2 * b + 1], 1ULL);
+        coh_store(&sl[SLOT_WORDS * b + 1], 1ULL);
       }
     }
     return;
@@ -305,12 +308,12 @@ __device__ inline void combine_slots(const RedK &R, T wg, T *lds) {
     long long spins = 0;
     for (;;) {
       if (INT) {
-        if (coh_load(&sl[2 * i + 1]) != 0ULL) {
-          bits = coh_load(&sl[2 * i]);
+        if (coh_load(&sl[SLOT_WORDS * i + 1]) != 0ULL) {
+          bits = coh_load(&sl[SLOT_WORDS * i]);
           break;
         }
       } else {
-        bits = coh_load(&sl[2 * i]);
+        bits = coh_load(&sl[SLOT_WORDS * i]);
         if (bits != SLOT_EMPTY) break;
       }
       __builtin_amdgcn_s_sleep(1);
@@ -320,8 +323,8 @@ __device__ inline void combine_slots(const RedK &R, T wg, T *lds) {
       }
     }
     v = red_apply(R.op, v, __builtin_bit_cast(T, bits));
-    coh_store(&sl[2 * i], INT ? 0ULL : SLOT_EMPTY);
-    if (INT) coh_store(&sl[2 * i + 1], 0ULL);
+    coh_store(&sl[SLOT_WORDS * i], INT ? 0ULL : SLOT_EMPTY);
+    if (INT) coh_store(&sl[SLOT_WORDS * i + 1], 0ULL);
   }
   if (threadIdx.x == 0) v = red_apply(R.op, v, wg);  // this workgroup's own value, last
   v = block_reduce(R.op, v, lds);
