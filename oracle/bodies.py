@@ -98,15 +98,32 @@ def jacobi5_sweep_f64(u0: np.ndarray) -> np.ndarray:
 
 def max_update_f64(u1: np.ndarray, u0: np.ndarray) -> float:
     """``max over the interior of |(double) u1 - (double) u0|`` (sec. 5 reduction, max)."""
+    return update_f64(u1, u0, "max")
+
+
+def update_f64(u1: np.ndarray, u0: np.ndarray, op: str = "max") -> float:
+    """Reduction of ``|(double) u1 - (double) u0|`` over the interior (sec. 5).
+
+    ``op`` is "max", "min" or "sum"; the sum is correctly rounded (fsum).
+    An interior with no points gives 0 for "max" and "sum" (the values are
+    non-negative) and +inf for "min".
+    """
     if u0.shape[0] < 3 or u0.shape[1] < 3:
-        return 0.0
+        return math.inf if op == "min" else 0.0
     d = np.abs(u1[1:-1, 1:-1].astype(np.float64) - u0[1:-1, 1:-1].astype(np.float64))
-    return float(d.max())
+    if op == "max":
+        return float(d.max())
+    if op == "min":
+        return float(d.min())
+    if op == "sum":
+        return math.fsum(d.ravel().tolist())
+    raise ValueError(op)
 
 
-def jacobi5(u0: np.ndarray, sweeps: int, mode: str = "f32"):
+def jacobi5(u0: np.ndarray, sweeps: int, mode: str = "f32", op: str = "max"):
     """``sweeps`` Jacobi sweeps; returns (final grid, residual per sweep).
 
+    The residual of a sweep is ``update_f64(new, old, op)``.
     mode "f32" reproduces float32 operation order exactly; mode "f64" runs
     the same recurrence in float64 (for error reports).
     """
@@ -115,7 +132,7 @@ def jacobi5(u0: np.ndarray, sweeps: int, mode: str = "f32"):
     res = []
     for _ in range(sweeps):
         u1 = step(u)
-        res.append(max_update_f64(u1, u))
+        res.append(update_f64(u1, u, op))
         u = u1
     return u, np.array(res, dtype=np.float64)
 

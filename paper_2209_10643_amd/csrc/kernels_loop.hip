@@ -306,14 +306,18 @@ hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, con
   return hipGetLastError();
 }
 
-// --------------------------------------------------------- Jacobi, LDS tiles
-// Tile = TH rows x 256 columns, anchored at multiples of (TH, 256). A team
-// stages rows i0-1 .. i0+TH and columns j0-1 .. j0+256 of src in LDS (only
-// the cells that in-box points read), then wavefront w computes tile rows
-// r = w, w + NW, ... with lane l on columns 4l .. 4l+3 -- the unit owning
-// 4-point group p/4 = r*64 + l is (p/4) mod U as the tiled schedule says.
-constexpr int JT_W = 256;          // tile width (points)
-constexpr int JT_S = JT_W + 8;     // LDS row stride (floats); core at +4
+// ----------------------------------------------- Jacobi, wavefront strips
+// Tile = TH rows x 256 columns, anchored at multiples of (TH, 256); tiles go
+// to teams by the schedule. Inside a team's tile the NW = U/64 wavefronts
+// take contiguous strips of ceil(TH/NW) rows and lane l takes columns
+// 4l .. 4l+3 of every row of its strip (the within-tile unit assignment of
+// this body). A wavefront walks its strip top to bottom holding the rows
+// above and at the current one in registers, loads the rows below in groups
+// of JG (all in flight together), and gets its west/east neighbours from the
+// adjacent lanes (lane 0 and lane 63 load the tile's halo columns). Nothing
+// is staged in LDS, so no barrier separates loads from arithmetic.
+constexpr int JT_W = 256;  // tile width (points)
+constexpr int JG = 8;      // rows loaded together per wavefront
 
 // Residual reduction per lane. The float64 value of |u1 - u0| is only needed
 // where it can change the lane's maximum (or minimum): rounding to float32
@@ -342,12 +346,85 @@ struct ResidualAcc {
   }
 };
 
+// One row segment of a wavefront: the lane's four columns (c0 .. c0+3) and,
+// in `h`, lane 0's west halo (column c0-1) or lane 63's east halo (column
+// c0+4). EDGE loads only the columns [clo, chi] that in-box points read.
+template <bool EDGE>
+__device__ __forceinline__ void jacobi_load_row(const float *row, int64_t c0, int lane, int64_t clo, int64_t chi, f32x4 &v,
+                                       float &h) {
+  if (!EDGE || (c0 >= clo && c0 + 3 <= chi)) {
+    v = *(const f32x4 *)(row + c0);
+  } else {
+    float e[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) e[q] = (c0 + q >= clo && c0 + q <= chi) ? row[c0 + q] : 0.0f;
+    v = f32x4{e[0], e[1], e[2], e[3]};
+  }
+  const int64_t hc = lane == 0 ? c0 - 1 : c0 + 4;
+  h = 0.0f;
+  if ((lane == 0 || lane == WAVE - 1) && hc >= clo && hc <= chi) h = row[hc];
+}
+
+// Rows [ra, rb) of one wavefront's strip, columns of this lane. EDGE is the
+// path of tiles that cross the loop box's column bounds [jlo, jhi).
+template <bool EDGE, int RED>
+__device__ __forceinline__ void jacobi_strip(const JacobiP &p, int64_t ra, int64_t rb, int64_t c0, int lane, int64_t clo,
+                                    int64_t chi, int64_t jlo, int64_t jhi, ResidualAcc<RED> &acc) {
+  const int64_t ld = p.ld;
+  f32x4 up, mid;
+  float hu, hm;
+  jacobi_load_row<EDGE>(p.src + (ra - 1) * ld, c0, lane, clo, chi, up, hu);
+  jacobi_load_row<EDGE>(p.src + ra * ld, c0, lane, clo, chi, mid, hm);
+  for (int64_t r = ra; r < rb; r += JG) {
+    f32x4 dn[JG];
+    float hd[JG];
+#pragma unroll
+    for (int q = 0; q < JG; ++q) {  // rows r+1 .. r+JG, clamped to rb (in the box's halo)
+      const int64_t rr = r + 1 + q < rb ? r + 1 + q : rb;
+      jacobi_load_row<EDGE>(p.src + rr * ld, c0, lane, clo, chi, dn[q], hd[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < JG; ++q) {
+      if (r + q >= rb) break;
+      const float wsh = __shfl_up(mid.w, 1), esh = __shfl_down(mid.x, 1);
+      const float Wm = lane == 0 ? hm : wsh, Ep = lane == WAVE - 1 ? hm : esh;
+      const f32x4 S = dn[q];
+      f32x4 v;
+      v.x = ((up.x + S.x) + (Wm + mid.y)) * 0.25f;
+      v.y = ((up.y + S.y) + (mid.x + mid.z)) * 0.25f;
+      v.z = ((up.z + S.z) + (mid.y + mid.w)) * 0.25f;
+      v.w = ((up.w + S.w) + (mid.z + Ep)) * 0.25f;
+      float *out = p.dst + (r + q) * ld + c0;
+      if (!EDGE || (c0 >= jlo && c0 + 3 < jhi)) {
+        *(f32x4 *)out = v;
+        if (RED) {
+          acc.add(v.x, mid.x);
+          acc.add(v.y, mid.y);
+          acc.add(v.z, mid.z);
+          acc.add(v.w, mid.w);
+        }
+      } else {
+        const float vv[4] = {v.x, v.y, v.z, v.w}, cc[4] = {mid.x, mid.y, mid.z, mid.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (c0 + e >= jlo && c0 + e < jhi) {
+            out[e] = vv[e];
+            if (RED) acc.add(vv[e], cc[e]);
+          }
+        }
+      }
+      up = mid;
+      mid = S;
+      hm = hd[q];
+    }
+  }
+}
+
 template <int TH, int RED>
 __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP p, RedK R) {
-  extern __shared__ float lds[];
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, NW = blockDim.x / WAVE;
   const int team = xcd_team(blockIdx.x, gridDim.x);
-  const int64_t ld = p.ld;
+  const int SH = (TH + NW - 1) / NW;                          // strip height
   const int64_t ilo = L.lb[0], ihi = L.lb[0] + L.cnt[0];  // interior rows [ilo, ihi)
   const int64_t jlo = L.lb[1], jhi = L.lb[1] + L.cnt[1];
   ResidualAcc<RED> acc;
@@ -355,58 +432,16 @@ __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP
   auto do_tile = [&](int64_t m) {
     const int64_t ti = S.t0[0] + m / S.nt[1], tj = S.t0[1] + m % S.nt[1];
     const int64_t i0 = ti * TH, j0 = tj * JT_W;
-    // rows / cols read by in-box points of this tile
-    const int64_t rlo = (i0 > ilo ? i0 : ilo) - 1, rhi = (i0 + TH < ihi ? i0 + TH : ihi);      // inclusive
-    const int64_t clo = (j0 > jlo ? j0 : jlo) - 1, chi = (j0 + JT_W < jhi ? j0 + JT_W : jhi);  // inclusive
-    __syncthreads();
-    for (int rr = w; rr < TH + 2; rr += NW) {
-      const int64_t gi = i0 - 1 + rr;
-      if (gi < rlo || gi > rhi) continue;
-      const float *row = p.src + gi * ld;
-      float *lrow = lds + rr * JT_S;
-      const int64_t c0 = j0 + 4 * lane;
-      if (c0 >= clo && c0 + 3 <= chi) {
-        *(f32x4 *)(lrow + 4 + 4 * lane) = *(const f32x4 *)(row + c0);
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (c0 + q >= clo && c0 + q <= chi) lrow[4 + 4 * lane + q] = row[c0 + q];
-      }
-      if (lane == 0 && j0 - 1 >= clo) lrow[3] = row[j0 - 1];
-      if (lane == 1 && j0 + JT_W <= chi) lrow[4 + JT_W] = row[j0 + JT_W];
-    }
-    __syncthreads();
-    for (int r = w; r < TH; r += NW) {
-      const int64_t i = i0 + r;
-      if (i < ilo || i >= ihi) continue;
-      const float *up = lds + r * JT_S + 4, *mid = lds + (r + 1) * JT_S + 4, *dn = lds + (r + 2) * JT_S + 4;
-      const int c = 4 * lane;
-      const f32x4 N = *(const f32x4 *)(up + c), Sv = *(const f32x4 *)(dn + c), C = *(const f32x4 *)(mid + c);
-      const float Wm = mid[c - 1], Ep = mid[c + 4];
-      f32x4 v;
-      v.x = ((N.x + Sv.x) + (Wm + C.y)) * 0.25f;
-      v.y = ((N.y + Sv.y) + (C.x + C.z)) * 0.25f;
-      v.z = ((N.z + Sv.z) + (C.y + C.w)) * 0.25f;
-      v.w = ((N.w + Sv.w) + (C.z + Ep)) * 0.25f;
-      const int64_t j = j0 + c;
-      float *out = p.dst + i * ld + j;
-      const float vv[4] = {v.x, v.y, v.z, v.w};
-      const float cc[4] = {C.x, C.y, C.z, C.w};
-      if (j >= jlo && j + 3 < jhi) {
-        *(f32x4 *)out = v;
-        if (RED) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc.add(vv[q], cc[q]);
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (j + q >= jlo && j + q < jhi) {
-            out[q] = vv[q];
-            if (RED) acc.add(vv[q], cc[q]);
-          }
-        }
-      }
+    const int64_t s0 = i0 + (int64_t)w * SH, s1 = s0 + SH < i0 + TH ? s0 + SH : i0 + TH;
+    const int64_t ra = s0 > ilo ? s0 : ilo, rb = s1 < ihi ? s1 : ihi;
+    if (ra >= rb) return;
+    const int64_t c0 = j0 + 4 * lane;
+    if (j0 >= jlo && j0 + JT_W <= jhi) {
+      jacobi_strip<false, RED>(p, ra, rb, c0, lane, j0 - 1, j0 + JT_W, jlo, jhi, acc);
+    } else {
+      // columns read by in-box points of this tile (inclusive)
+      const int64_t clo = (j0 > jlo ? j0 : jlo) - 1, chi = (j0 + JT_W < jhi ? j0 + JT_W : jhi);
+      jacobi_strip<true, RED>(p, ra, rb, c0, lane, clo, chi, jlo, jhi, acc);
     }
   };
 
@@ -437,7 +472,7 @@ bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
 
 template <int TH>
 static hipError_t go_jacobi(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
-  const size_t lds = (size_t)(TH + 2) * JT_S * sizeof(float);
+  const size_t lds = 0;
   switch (R.op) {
     case RED_NONE: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_NONE>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R); break;
     case RED_SUM: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_SUM>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R); break;

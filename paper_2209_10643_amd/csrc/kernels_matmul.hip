@@ -121,17 +121,16 @@ __device__ inline void for_team_tiles(const SchedK &S, F &&f) {
   }
 }
 
-template <int NPROD, int BM, int BN, int WM, int WN, int BK>
+template <int NPROD, int BM, int BN, int WM, int WN, int BK, int STAGES>
 __global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
   constexpr int NTH = WM * WN * 64;
   constexpr int PITCH = BK + 8;  // halfwords per LDS row (16-byte multiple)
   constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
   constexpr int CPR = BK / 8;                    // 16-byte chunks per row
   constexpr int CA = BM * CPR / NTH, CB = BN * CPR / NTH;
+  constexpr int STAGE = (NPROD == 3 ? 2 : 1) * (BM + BN) * PITCH;  // halfwords per LDS stage
   static_assert(BM * CPR % NTH == 0 && BN * CPR % NTH == 0, "chunk split");
   extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
-  uint16_t *sAh = lds, *sBh = lds + BM * PITCH;
-  uint16_t *sAl = sBh + BN * PITCH, *sBl = sAl + BM * PITCH;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int64_t K = p.K;
@@ -162,7 +161,10 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
         if (NPROD == 3) rbl[q] = in ? *(const u32x4 *)(p.bl + gc * K + gk) : u32x4{};
       }
     };
-    auto stage = [&]() {
+    // LDS stage layout: A_hi (BM rows), B_hi (BN rows), then A_lo, B_lo
+    auto stage = [&](int buf) {
+      uint16_t *sAh = lds + buf * STAGE, *sBh = sAh + BM * PITCH;
+      uint16_t *sAl = sBh + BN * PITCH, *sBl = sAl + BM * PITCH;
 #pragma unroll
       for (int q = 0; q < CA; ++q) {
         const int c = tid + q * NTH, r = c / CPR, kc = c % CPR;
@@ -178,11 +180,14 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
     };
     __syncthreads();  // previous tile's readers are done with LDS
     fetch(0);
-    stage();
+    stage(0);
     __syncthreads();
+    int cur = 0;
     for (int64_t k0 = 0; k0 < K; k0 += BK) {
       const bool more = k0 + BK < K;
       if (more) fetch(k0 + BK);
+      const uint16_t *sAh = lds + cur * STAGE, *sBh = sAh + BM * PITCH;
+      const uint16_t *sAl = sBh + BN * PITCH, *sBl = sAl + BM * PITCH;
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 16) {
         const int koff = ks + 8 * (lane >> 5);
@@ -210,9 +215,14 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
           }
       }
-      if (more) {
+      if (STAGES == 2) {
+        // the other buffer was last read before the previous barrier
+        if (more) stage(cur ^ 1);
         __syncthreads();
-        stage();
+        cur ^= 1;
+      } else if (more) {
+        __syncthreads();
+        stage(0);
         __syncthreads();
       }
     }
@@ -346,13 +356,14 @@ static hipError_t go_mm(Kern k, const MatmulP &p, const SchedK &S, size_t lds, h
 
 hipError_t launch_matmul_mfma(const MatmulP &p, const LoopK &, const SchedK &S, hipStream_t st) {
   const int bm = S.tile[0], bn = S.tile[1];
+  // LDS bytes = stages x (BM + BN) rows x pitch x 2 bytes (x 2 for the lo halves)
   if (p.kind == UPIR_BODY_MATMUL_BF16) {
-    if (bm == 256) return go_mm(k_mm_bf16<1, 256, 256, 2, 4, 64>, p, S, 2 * 256 * 72 * 2, st);
-    return go_mm(k_mm_bf16<1, 128, 128, 2, 2, 64>, p, S, 2 * 128 * 72 * 2, st);
+    if (bm == 256) return go_mm(k_mm_bf16<1, 256, 256, 2, 4, 64, 2>, p, S, 2 * (256 + 256) * 72 * 2, st);
+    return go_mm(k_mm_bf16<1, 128, 128, 2, 2, 64, 2>, p, S, 2 * (128 + 128) * 72 * 2, st);
   }
   if (p.kind == UPIR_BODY_MATMUL_SPLIT3) {
-    if (bm == 256) return go_mm(k_mm_bf16<3, 256, 256, 2, 4, 32>, p, S, 4 * 256 * 40 * 2, st);
-    return go_mm(k_mm_bf16<3, 128, 128, 2, 2, 32>, p, S, 4 * 128 * 40 * 2, st);
+    if (bm == 256) return go_mm(k_mm_bf16<3, 256, 256, 2, 4, 32, 1>, p, S, 2 * (256 + 256) * 40 * 2, st);
+    return go_mm(k_mm_bf16<3, 128, 128, 2, 2, 32, 2>, p, S, 2 * 2 * (128 + 128) * 40 * 2, st);
   }
   if (bm == 256 && bn == 128) return go_mm(k_mm_f32<256, 128, 4, 2, 32>, p, S, (256 * 36 + 32 * 136) * 4, st);
   return go_mm(k_mm_f32<128, 128, 2, 2, 32>, p, S, (128 * 36 + 32 * 136) * 4, st);

@@ -302,29 +302,48 @@ __device__ inline void combine_slots(const RedK &R, T wg, T *lds) {
   __shared__ int s_missing;
   if (threadIdx.x == 0) s_missing = 0;
   __syncthreads();
+  // Each thread folds slots tid, tid + U, tid + 2U, ... in that order. The
+  // slots of a batch are loaded together (one memory round trip for the
+  // batch); only slots that are still empty are polled again.
+  constexpr int BATCH = 8;
+  const int U = blockDim.x;
   T v = red_identity<T>(R.op);
-  for (int i = threadIdx.x; i < G - 1; i += blockDim.x) {
-    unsigned long long bits = 0;
-    long long spins = 0;
-    for (;;) {
-      if (INT) {
-        if (coh_load(&sl[SLOT_WORDS * i + 1]) != 0ULL) {
-          bits = coh_load(&sl[SLOT_WORDS * i]);
+  for (int i0 = threadIdx.x; i0 < G - 1; i0 += BATCH * U) {
+    unsigned long long bits[BATCH];
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int i = i0 + q * U;
+      bits[q] = i < G - 1 ? coh_load(&sl[SLOT_WORDS * i + (INT ? 1 : 0)]) : 0ULL;
+    }
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int i = i0 + q * U;
+      if (i >= G - 1) break;
+      long long spins = 0;
+      while (INT ? bits[q] == 0ULL : bits[q] == SLOT_EMPTY) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > R.spin_limit) {
+          s_missing = 1;
           break;
         }
-      } else {
-        bits = coh_load(&sl[SLOT_WORDS * i]);
-        if (bits != SLOT_EMPTY) break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > R.spin_limit) {
-        s_missing = 1;
-        break;
+        bits[q] = coh_load(&sl[SLOT_WORDS * i + (INT ? 1 : 0)]);
       }
     }
-    v = red_apply(R.op, v, __builtin_bit_cast(T, bits));
-    coh_store(&sl[SLOT_WORDS * i], INT ? 0ULL : SLOT_EMPTY);
-    if (INT) coh_store(&sl[SLOT_WORDS * i + 1], 0ULL);
+    if (INT) {  // flags seen: now the values
+#pragma unroll
+      for (int q = 0; q < BATCH; ++q) {
+        const int i = i0 + q * U;
+        if (i < G - 1) bits[q] = coh_load(&sl[SLOT_WORDS * i]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int i = i0 + q * U;
+      if (i >= G - 1) break;
+      v = red_apply(R.op, v, __builtin_bit_cast(T, bits[q]));
+      coh_store(&sl[SLOT_WORDS * i], INT ? 0ULL : SLOT_EMPTY);
+      if (INT) coh_store(&sl[SLOT_WORDS * i + 1], 0ULL);
+    }
   }
   if (threadIdx.x == 0) v = red_apply(R.op, v, wg);  // this workgroup's own value, last
   v = block_reduce(R.op, v, lds);

@@ -224,7 +224,7 @@ def jacobi_grid(H_, W, seed=7):
     return u
 
 
-def run_jacobi(ctx, u0, sweeps, sched, spmd=None, graph=False, replays=1):
+def run_jacobi(ctx, u0, sweeps, sched, spmd=None, graph=False, replays=1, op=None):
     Hh, W = u0.shape
     a, b = dev(u0), dev(u0)
     res = torch.zeros(sweeps, dtype=torch.float64, device="cuda")
@@ -233,7 +233,8 @@ def run_jacobi(ctx, u0, sweeps, sched, spmd=None, graph=False, replays=1):
     for k in range(sweeps):
         src, dst = (a, b) if k % 2 == 0 else (b, a)
         args = U.upir_jacobi5_args(src.data_ptr(), dst.data_ptr(), W)
-        red = H.make_red(U.UPIR_RED_MAX, res[k:].data_ptr())
+        op_ = U.UPIR_RED_MAX if op is None else op
+        red = H.make_red(op_, res[k:].data_ptr(), init=float("inf") if op_ == U.UPIR_RED_MIN else 0.0)
         handles.append(ctx.loop(U.UPIR_BODY_JACOBI5, args, dims, sched, red))
     variant = ctx.resolve(handles[0], spmd)[2]
     outs = []
@@ -288,6 +289,32 @@ def test_jacobi_parity(ctx, shape, sched, spmd, variant):
     got_u, got_r = outs[0]
     assert np.array_equal(got_u, want_u)
     assert np.array_equal(got_r, want_r)
+
+
+OPS = {"max": U.UPIR_RED_MAX, "min": U.UPIR_RED_MIN, "sum": U.UPIR_RED_SUM}
+
+
+@pytest.mark.parametrize("th,units,op", [
+    (4, 64, "max"), (16, 192, "max"), (64, 64, "max"), (64, 512, "min"), (8, 256, "sum"), (32, 128, "sum"),
+    (32, 256, "min"),
+])
+def test_jacobi_tile_strips_and_ops(ctx, th, units, op):
+    """Tile heights, wavefront counts (192: strips of unequal length) and the
+    three residual reductions on a grid with ragged tiles on all sides."""
+    note(f"jacobi tile ({th}, 256) units {units} op {op}")
+    u0 = jacobi_grid(203, 780, seed=th + units)
+    sched = H.make_sched(U.UPIR_SCHED_STATIC, tile=(th, 256))
+    outs, v = run_jacobi(ctx, u0, 3, sched, H.make_spmd(0, units), op=OPS[op])
+    assert U.VARIANTS[v] == "jacobi_tile"
+    want_u, want_r = bodies.jacobi5(u0, 3, op=op)
+    got_u, got_r = outs[0]
+    assert np.array_equal(got_u, want_u)
+    if op == "sum":
+        # float64 sum of n non-negative terms in another order: |error| <= n 2^-53 sum
+        n = (u0.shape[0] - 2) * (u0.shape[1] - 2)
+        assert np.all(np.abs(got_r - want_r) <= n * 2.0 ** -53 * want_r)
+    else:
+        assert np.array_equal(got_r, want_r)
 
 
 def test_jacobi_linear_field_is_fixed(ctx):

@@ -119,6 +119,37 @@ def test_jacobi_brute_force(H, W):
     assert res.tolist() == rr
 
 
+@pytest.mark.parametrize("H,W", [(5, 7), (9, 4)])
+def test_jacobi_min_and_sum_residual_brute_force(H, W):
+    """min and sum of |u1 - u0| point by point; the sum is compared with the
+    exact rational sum rounded once (what a correctly rounded sum returns)."""
+    from fractions import Fraction
+    u = synth.uniform_01(5, 1, H * W).reshape(H, W)
+    u[0, :] = u[-1, :] = 0
+    u[:, 0] = u[:, -1] = 0
+    _, rmin = bodies.jacobi5(u, 2, op="min")
+    _, rsum = bodies.jacobi5(u, 2, op="sum")
+    ref = u.copy()
+    for k in range(2):
+        nxt = _jacobi_brute(ref)
+        ds = [abs(Fraction(float(nxt[i, j])) - Fraction(float(ref[i, j])))
+              for i in range(1, H - 1) for j in range(1, W - 1)]
+        assert rmin[k] == float(min(ds))
+        assert rsum[k] == float(sum(ds))
+        ref = nxt
+
+
+def test_jacobi_residual_ops_on_impulse_and_empty():
+    u = np.zeros((7, 7), np.float32)
+    u[3, 3] = 1
+    # one sweep: the impulse point drops by 1, its four neighbours rise by 1/4
+    assert bodies.jacobi5(u, 1, op="sum")[1][0] == 2.0
+    assert bodies.jacobi5(u, 1, op="min")[1][0] == 0.0
+    e = np.zeros((2, 5), np.float32)
+    assert bodies.update_f64(e, e, "min") == math.inf
+    assert bodies.update_f64(e, e, "sum") == 0.0 == bodies.update_f64(e, e, "max")
+
+
 def test_jacobi_linear_field_fixed_point():
     N = 64
     i, j = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
