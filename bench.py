@@ -1,6 +1,6 @@
 """Benchmark of the UPIR data-parallel loop library on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--configs 1,0,2,3,4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--configs 1,1L,0,2,3,4]
                     [--no-cpu-baseline]
 
 One step = one pass of the headline workload: a 4096 x 4096 float32 Jacobi
@@ -65,7 +65,11 @@ class Timer:
 class JacobiWork:
     N, SWEEPS = 4096, 100
 
-    def __init__(self, torch, ctx, seed=12345, tune=True):
+    def __init__(self, torch, ctx, seed=12345, tune=True, N=None, sweeps=None):
+        if N is not None:
+            self.N = N
+        if sweeps is not None:
+            self.SWEEPS = sweeps
         N = self.N
         self.tuned_us = None
         u = synth.uniform_01_torch(seed, 0, N * N, device="cuda").reshape(N, N)
@@ -82,7 +86,9 @@ class JacobiWork:
         for k in range(self.SWEEPS):
             src, dst = (self.a, self.b) if k % 2 == 0 else (self.b, self.a)
             args = U.upir_jacobi5_args(src.data_ptr(), dst.data_ptr(), N)
-            red = H.make_red(U.UPIR_RED_MAX, self.res[k:].data_ptr())
+            # async: each sweep's residual fold rides on the next sweep's kernel;
+            # the last one is a fold node at the end of the graph
+            red = H.make_red(U.UPIR_RED_MAX, self.res[k:].data_ptr(), async_=True)
             self.handles.append(ctx.loop(U.UPIR_BODY_JACOBI5, args, dims, None, red))
         if tune:  # schedule(auto): the exhaustive tuner picks tile, units and teams
             best_us = C.c_double()
@@ -91,7 +97,7 @@ class JacobiWork:
         sp, sc, v = ctx.resolve(self.handles[0])
         self.variant = U.VARIANTS[v]
         self.teams, self.units, self.tile = sp.num_teams, sp.num_units, (sc.tile[0], sc.tile[1])
-        ctx.launch(self.handles[:1])
+        ctx.launch(self.handles)  # every handle sized once before capture
         ctx.sync()
         ctx.graph_begin()
         ctx.launch(self.handles)
@@ -112,6 +118,34 @@ class JacobiWork:
         self.ctx.graph_destroy(self.graph)
         for h in self.handles:
             self.ctx.free(h)
+
+
+def bench_jacobi_large(torch, ctx, N=16384, sweeps=10, reps=3):
+    """Jacobi where the two grids (2 x 1 GiB) exceed the 256 MB MALL: every
+    sweep streams from HBM. Schedule auto (tuned), graph of `sweeps` sweeps."""
+    jw = JacobiWork(torch, ctx, seed=777, N=N, sweeps=sweeps)
+    jw.reset()
+    jw.step()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        jw.reset()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        jw.step()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ms = sorted(ts)[len(ts) // 2]
+    out = {"grid": [N, N], "sweeps": sweeps, "variant": jw.variant, "tile": list(jw.tile), "teams": jw.teams,
+           "units": jw.units, "ms_median": round(ms, 3), "ms_min": round(min(ts), 3),
+           "GBps": round(sweeps * jw.bytes_per_sweep() / (ms * 1e-3) / 1e9, 1),
+           "working_set_MiB": 2 * N * N * 4 >> 20, "note": "exceeds the MALL: HBM-bound"}
+    jw.close()
+    del jw
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline_jacobi(seed=12345, sweeps=40):
@@ -486,7 +520,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--configs", default="1,0,2,3,4")
+    ap.add_argument("--configs", default="1,1L,0,2,3,4",
+                    help="1 Jacobi 4096^2 (always timed: the headline), 1L Jacobi 16384^2, 0 AXPY+sum, "
+                         "2 matmul, 3 batched tasks, 4 learned schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (known bytes) to scale HBM counters")
@@ -539,7 +575,7 @@ def main():
     ach = jw.bytes_per_sweep() / (sweep_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"k_jacobi_tile<{jw.tile[0]},RED_MAX> ({jw.units} units)", "avg_launch_us": round(sweep_ms * 1e3, 3),
+                "kernel": f"k_jacobi_tile<{jw.tile[0]},RED_MAX> ({jw.units} units, deferred fold)", "avg_launch_us": round(sweep_ms * 1e3, 3),
                 "algorithmic_bytes_per_launch": jw.bytes_per_sweep()}
     res = jw.res.cpu().numpy()
     extras["jacobi"] = {"grid": [4096, 4096], "sweeps": 100, "variant": jw.variant, "tile": list(jw.tile),
@@ -547,6 +583,9 @@ def main():
                         "teams": jw.teams, "units": jw.units, "res_first": float(res[0]), "res_last": float(res[-1]),
                         "working_set_MiB": 128, "note": "two 64 MiB grids fit the 256 MB MALL"}
 
+    if "1L" in configs:
+        log("jacobi 16384^2 (beyond the MALL)")
+        extras["jacobi_16384"] = bench_jacobi_large(torch, ctx)
     if "0" in configs:
         log("axpy")
         extras["axpy_sum"] = bench_axpy(torch, ctx, timer)
@@ -571,8 +610,8 @@ def main():
         "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded SplitMix64 generators)",
-        "config": {"workload": "jacobi5 4096x4096 float32, 100 sweeps, collapse(2), max-residual float64, "
-                               "hipGraph replay", "parallelism": "single GPU"},
+        "config": {"workload": "jacobi5 4096x4096 float32, 100 sweeps, collapse(2), max-residual float64 "
+                               "per sweep (async fold), hipGraph replay", "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extras": extras,

@@ -164,8 +164,16 @@ typedef struct {
                                 upir_reduce_wait (or at launch if !async) */
     double init;             /* folded in once */
     void *result;            /* double (float data) or int64_t (integer data) */
-    int32_t async;           /* 1: launch = arrive-compute only; the caller
-                                must call upir_reduce_wait (wait-release) */
+    int32_t async;           /* 1: launch = arrive-compute only (sec. 5 split
+                                sync): the kernel leaves one partial per
+                                wavefront and the cross-workgroup fold is
+                                deferred to the next loop kernel on the
+                                context (its workgroup 0) or to the next
+                                upir_reduce_wait / upir_sync / graph end /
+                                taskwait / data_update / unmap (wait-release).
+                                A device result is valid after that point, a
+                                host result after upir_reduce_wait. Loops run
+                                as tasks ignore the flag. */
     int32_t pad_;
 } upir_reduction;
 

@@ -110,6 +110,7 @@ __global__ void __launch_bounds__(1024) k_generic(LoopK L, SchedK S, RedK R, B b
   else
     for_owned_untiled(L, S, team, unit, f);
   if (R.op != RED_NONE) finish_reduction<A>(R, acc);
+  fold_hook(R);
 }
 
 // Dynamic / guided: each team claims a range of iterations from a device
@@ -167,6 +168,7 @@ __global__ void __launch_bounds__(1024) k_dynamic(LoopK L, SchedK S, RedK R, B b
     }
   }
   if (R.op != RED_NONE) finish_reduction<A>(R, acc);
+  fold_hook(R);
 }
 
 template <class B>
@@ -279,6 +281,7 @@ __global__ void __launch_bounds__(1024) k_stream4(int64_t n, float a, const floa
       for (int64_t i = nc * 4; i < n; ++i) atomicAdd(&cnt[i], 1);
   }
   if (RED) finish_reduction<float>(R, acc);
+  fold_hook(R);
 }
 
 hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, const SchedK &S, const RedK &R,
@@ -455,6 +458,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP
       for (int64_t m = m0; m < m0 + c && m < S.ntiles; ++m) do_tile(m);
   }
   if (RED) finish_reduction<double>(R, acc.m64);
+  fold_hook(R);
 }
 
 bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
@@ -531,6 +535,7 @@ __global__ void __launch_bounds__(1024) k_matvec(LoopK L, SchedK S, MatvecP p, R
   };
   for_owned_untiled(L, SW, blockIdx.x, w, row);
   if (RED) finish_reduction<float>(R, acc);
+  fold_hook(R);
 }
 
 hipError_t launch_matvec_wave(const MatvecP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
@@ -541,4 +546,13 @@ hipError_t launch_matvec_wave(const MatvecP &p, const LoopK &L, const SchedK &S,
   return hipGetLastError();
 }
 
+}  // namespace upir
+
+// Standalone fold of a deferred reduction (one workgroup).
+namespace upir {
+__global__ void __launch_bounds__(256) k_fold(FoldK F) { run_fold(F); }
+hipError_t launch_fold(const FoldK &F, hipStream_t st) {
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(256), 0, st, F);
+  return hipGetLastError();
+}
 }  // namespace upir

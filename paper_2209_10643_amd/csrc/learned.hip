@@ -793,6 +793,10 @@ extern "C" upir_status upir_tune(upir_ctx *c, const upir_spmd *spmd, upir_loop_h
   if (c->none) return upir_fail(c, UPIR_ESTATE, "host-only context");
   if (c->capturing) return upir_fail(c, UPIR_ESTATE, "tuning during graph capture");
   if (reps < 1 || reps > 1000) return upir_fail(c, UPIR_EINVAL, "reps");
+  {
+    upir_status s0 = settle(c);
+    if (s0) return s0;
+  }
   // scratch copies of read-write outputs, and an internal reduction result
   upir_loop_obj tmp = *lp;
   tmp.scratch = nullptr;
@@ -809,6 +813,7 @@ extern "C" upir_status upir_tune(upir_ctx *c, const upir_spmd *spmd, upir_loop_h
     return p;
   };
   auto cleanup = [&]() {
+    (void)settle(c);  // a deferred fold of the copy writes into its scratch
     (void)hipStreamSynchronize(c->stream);
     for (void *p : owned) upir_dfree(c, p);
     upir_dfree(c, tmp.scratch);

@@ -135,7 +135,10 @@ static void free_loop(upir_ctx *c, upir_loop_obj *lp) {
 
 extern "C" upir_status upir_finalize(upir_ctx *c) {
   if (!c) return UPIR_EINVAL;
-  if (!c->none && c->stream) (void)hipStreamSynchronize(c->stream);
+  if (!c->none && c->stream) {
+    if (!c->capturing) (void)upir::settle(c);
+    (void)hipStreamSynchronize(c->stream);
+  }
   for (auto *g : c->graphs) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
@@ -145,6 +148,9 @@ extern "C" upir_status upir_finalize(upir_ctx *c) {
   for (auto *lp : c->loops) free_loop(c, lp);
   for (auto &kv : c->table) upir_dfree(c, kv.second.dev);
   upir_dfree(c, c->trace_clock);
+  upir_dfree(c, c->fold_buf[0]);
+  upir_dfree(c, c->fold_buf[1]);
+  for (void *p : c->retired) upir_dfree(c, p);
   upir_model_free(c);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -155,6 +161,8 @@ extern "C" upir_status upir_sync(upir_ctx *c) {
   if (!c) return UPIR_EINVAL;
   if (c->none) return upir_fail(c, UPIR_ESTATE, "host-only context");
   if (c->capturing) return upir_fail(c, UPIR_ESTATE, "cannot synchronise during graph capture");
+  upir_status st = upir::settle(c);
+  if (st) return st;
   HIPTRY(c, hipStreamSynchronize(c->stream));
   return UPIR_OK;
 }
@@ -212,6 +220,10 @@ extern "C" upir_status upir_data_unmap(upir_ctx *c, void *host, int32_t map) {
   auto it = c->table.find((uintptr_t)host);
   if (it == c->table.end()) return upir_fail(c, UPIR_ENOTMAPPED, "data_unmap: %p does not start a mapping", host);
   Mapping &m = it->second;
+  if (m.refs == 1 && !c->none) {  // a deferred result may live in this buffer
+    upir_status st = upir::settle(c);
+    if (st) return st;
+  }
   if (--m.refs > 0) return UPIR_OK;
   if (!c->none && (map == UPIR_MAP_FROM || map == UPIR_MAP_TOFROM) && m.access != UPIR_ACCESS_RO) {
     hipError_t e = hipMemcpyAsync(host, m.dev, m.bytes, hipMemcpyDeviceToHost, c->stream);
@@ -248,6 +260,8 @@ extern "C" upir_status upir_data_update(upir_ctx *c, void *host, size_t bytes, i
   if (dir == UPIR_TO_DEVICE) {
     HIPTRY(c, hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->stream));
   } else {
+    upir_status st = upir::settle(c);
+    if (st) return st;
     HIPTRY(c, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
     HIPTRY(c, hipStreamSynchronize(c->stream));
   }
@@ -456,6 +470,11 @@ extern "C" upir_status upir_loop_free(upir_ctx *c, upir_loop_h lp) {
   if (!c->loops.count(lp)) return upir_fail(c, UPIR_EINVAL, "unknown loop handle");
   for (auto &t : c->tasks)
     if (t.loop == lp) return upir_fail(c, UPIR_ESTATE, "loop handle is used by a pending task");
+  if (c->pend.on && c->pend.owner == lp) {
+    if (c->capturing) return upir_fail(c, UPIR_ESTATE, "loop has a deferred fold in the capture");
+    upir_status st = upir::settle(c);
+    if (st) return st;
+  }
   if (!c->none) (void)hipStreamSynchronize(c->stream);
   c->loops.erase(lp);
   if (c->reduce_loop == lp) c->reduce_loop = nullptr;
@@ -824,6 +843,10 @@ upir_status clear_scratch(upir_ctx *c, upir_loop_obj *lp, unsigned char *scr, in
 upir_status ensure_scratch(upir_ctx *c, upir_loop_obj *lp, int64_t parts) {
   if (parts <= lp->part_cap) return UPIR_OK;
   if (c->capturing) return upir_fail(c, UPIR_ESTATE, "reduction scratch must grow; launch once before capturing");
+  if (c->pend.on && c->pend.owner == lp) {
+    upir_status st = settle(c);
+    if (st) return st;
+  }
   HIPTRY(c, hipStreamSynchronize(c->stream));
   unsigned char *ns = (unsigned char *)upir_dalloc(c, scratch_bytes(parts));
   if (!ns) return upir_fail(c, UPIR_ENOMEM, "reduction scratch");
@@ -838,14 +861,53 @@ upir_status ensure_scratch(upir_ctx *c, upir_loop_obj *lp, int64_t parts) {
   return UPIR_OK;
 }
 
+upir_status settle(upir_ctx *c) {
+  if (!c->pend.on) return UPIR_OK;
+  hipError_t e = launch_fold(c->pend.F, c->stream);
+  if (e != hipSuccess) return upir_hipfail(c, e, "reduction fold");
+  c->pend.on = false;
+  c->pend.owner = nullptr;
+  return UPIR_OK;
+}
+
+// Both fold buffers hold at least `parts` partials. Outgrown buffers are
+// kept until finalize: a captured graph may still write them.
+static upir_status ensure_fold_bufs(upir_ctx *c, int64_t parts) {
+  if (parts <= c->fold_cap) return UPIR_OK;
+  if (c->capturing) return upir_fail(c, UPIR_ESTATE, "fold buffers must grow; launch once before capturing");
+  const int64_t cap = std::max<int64_t>(parts, 1 << 16);
+  unsigned long long *nb[2];
+  for (int i = 0; i < 2; ++i) {
+    nb[i] = (unsigned long long *)upir_dalloc(c, (size_t)cap * 8);
+    if (!nb[i]) {
+      if (i) upir_dfree(c, nb[0]);
+      return upir_fail(c, UPIR_ENOMEM, "fold buffers");
+    }
+  }
+  for (int i = 0; i < 2; ++i) {
+    if (c->fold_buf[i]) c->retired.push_back(c->fold_buf[i]);
+    c->fold_buf[i] = nb[i];
+  }
+  c->fold_cap = cap;
+  return UPIR_OK;
+}
+
+static bool takes_fold(int32_t variant) { return variant != V_MATMUL_MFMA; }
+
 upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for_task) {
-  (void)for_task;
   alignas(16) unsigned char pay[sizeof(MatmulP) + 16];
   upir_status st = resolve_payload(c, lp, pay);
   if (st) return st;
+  // an async reduction outside the task graph defers its fold
+  const bool defer = lp->has_red && lp->red.async && !for_task;
+  const int64_t nparts = (int64_t)pl.S.T * ((pl.S.U + 63) / 64);
+  if (defer) {
+    st = ensure_fold_bufs(c, nparts);
+    if (st) return st;
+  }
   RedK R{};
   if (lp->has_red) {
-    st = ensure_scratch(c, lp, pl.S.T);
+    st = ensure_scratch(c, lp, defer ? 0 : pl.S.T);  // deferred: no combiner slots
     if (st) return st;
     R.op = lp->red.op;
     R.is_int = red_is_int(lp);
@@ -854,6 +916,15 @@ upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for
     R.result = lp->red.result_on_host ? (void *)(lp->scratch + SCR_RESULT) : lp->red.result;
     R.slots = (unsigned long long *)(lp->scratch + SCR_SLOTS);
     R.spin_limit = 1LL << 22;
+    if (defer) R.defer = c->fold_buf[c->fold_flip];
+  }
+  if (c->pend.on) {  // the previous async loop's fold rides on this kernel
+    if (takes_fold(pl.variant) && !(lp->n == 0 && !lp->has_red)) {
+      R.fold = c->pend.F;
+    } else {
+      st = settle(c);
+      if (st) return st;
+    }
   }
   SchedK S = pl.S;
   S.dyn_next = (long long *)(lp->scratch + SCR_DYN);
@@ -880,12 +951,32 @@ upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for
     }
   }
   if (e != hipSuccess) return upir_hipfail(c, e, "kernel launch");
+  if (R.fold.count > 0) {
+    c->pend.on = false;
+    c->pend.owner = nullptr;
+  }
+  if (defer) {
+    FoldK F{};
+    F.part = R.defer;
+    F.count = nparts;
+    F.op = R.op;
+    F.is_int = R.is_int;
+    F.init = R.init;
+    F.init_i = R.init_i;
+    F.result = R.result;
+    c->pend.on = true;
+    c->pend.F = F;
+    c->pend.owner = lp;
+    c->fold_flip ^= 1;
+  }
   return UPIR_OK;
 }
 
 }  // namespace upir
 
 static upir_status deliver_result(upir_ctx *c, upir_loop_obj *lp) {
+  upir_status st = upir::settle(c);
+  if (st) return st;
   HIPTRY(c, hipMemcpyAsync(lp->red.result, lp->scratch + SCR_RESULT, 8, hipMemcpyDeviceToHost, c->stream));
   HIPTRY(c, hipStreamSynchronize(c->stream));
   lp->pending = false;
@@ -934,6 +1025,8 @@ extern "C" upir_status upir_reduce_wait(upir_ctx *c, upir_loop_h lp) {
     if (!lp->pending) return upir_fail(c, UPIR_ESTATE, "no reduction in flight");
     return deliver_result(c, lp);
   }
+  upir_status st = upir::settle(c);
+  if (st) return st;
   HIPTRY(c, hipStreamSynchronize(c->stream));
   return UPIR_OK;
 }
@@ -987,6 +1080,8 @@ extern "C" upir_status upir_graph_begin(upir_ctx *c) {
   if (!c) return UPIR_EINVAL;
   if (c->none) return upir_fail(c, UPIR_ESTATE, "host-only context");
   if (c->capturing) return upir_fail(c, UPIR_ESTATE, "already capturing");
+  upir_status st = upir::settle(c);  // folds pending from eager launches stay outside the graph
+  if (st) return st;
   HIPTRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
   c->capturing = true;
   return UPIR_OK;
@@ -995,6 +1090,8 @@ extern "C" upir_status upir_graph_begin(upir_ctx *c) {
 extern "C" upir_status upir_graph_end(upir_ctx *c, upir_graph_h *out) {
   if (!c || !out) return UPIR_EINVAL;
   if (!c->capturing) return upir_fail(c, UPIR_ESTATE, "not capturing");
+  // the graph's last deferred fold is part of the graph
+  const upir_status fs = upir::settle(c);
   c->capturing = false;
   upir_graph_obj *g = new upir_graph_obj();
   hipError_t e = hipStreamEndCapture(c->stream, &g->graph);
@@ -1004,6 +1101,12 @@ extern "C" upir_status upir_graph_end(upir_ctx *c, upir_graph_h *out) {
     delete g;
     return upir_hipfail(c, e, "graph capture");
   }
+  if (fs) {
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return fs;
+  }
   c->graphs.insert(g);
   *out = g;
   return UPIR_OK;
@@ -1012,6 +1115,8 @@ extern "C" upir_status upir_graph_end(upir_ctx *c, upir_graph_h *out) {
 extern "C" upir_status upir_graph_launch(upir_ctx *c, upir_graph_h g) {
   if (!c || !g || !c->graphs.count(g)) return UPIR_EINVAL;
   if (c->capturing) return upir_fail(c, UPIR_ESTATE, "graph launch during capture");
+  upir_status st = upir::settle(c);  // the graph reuses the fold buffers
+  if (st) return st;
   HIPTRY(c, hipGraphLaunch(g->exec, c->stream));
   return UPIR_OK;
 }

@@ -80,6 +80,17 @@ struct TunedChoice {
 
 struct ModelState;  // cost model (learned.hip)
 
+// Deferred reduction folds (async reductions): a launch leaves one partial
+// per wavefront in fold_buf[fold_flip] and flips; the fold is run by
+// workgroup 0 of the next loop kernel on the stream, or by a one-workgroup
+// kernel at the next synchronisation point. Two buffers, so a kernel can
+// fold its predecessor's partials while writing its own.
+struct PendingFold {
+  bool on = false;
+  upir::FoldK F{};
+  upir_loop_obj *owner = nullptr;  // the loop that deferred it (F.result may be in its scratch)
+};
+
 struct upir_ctx {
   int device = -1;
   bool none = false;
@@ -105,6 +116,11 @@ struct upir_ctx {
   bool model_on = false;
   upir_loop_obj *reduce_loop = nullptr;  // cached handle for upir_reduce
   void *trace_clock = nullptr;           // device clock of the plain executor's trace
+  PendingFold pend;
+  unsigned long long *fold_buf[2] = {nullptr, nullptr};
+  int64_t fold_cap = 0;                  // partials per buffer
+  int fold_flip = 0;
+  std::vector<void *> retired;           // outgrown fold buffers (graphs may use them)
 };
 
 // helpers shared by the runtime translation units
@@ -125,6 +141,8 @@ struct Plan {
 upir_status resolve_plan(upir_ctx *c, const upir_spmd *spmd, upir_loop_obj *lp, Plan &out);
 upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for_task);
 upir_status ensure_scratch(upir_ctx *c, upir_loop_obj *lp, int64_t parts);
+// Run a pending deferred fold now (a one-workgroup kernel on the stream).
+upir_status settle(upir_ctx *c);
 upir_status clear_scratch(upir_ctx *c, upir_loop_obj *lp, unsigned char *scr, int64_t cap);
 bool red_is_int(const upir_loop_obj *lp);
 upir_status resolve_payload(upir_ctx *c, upir_loop_obj *lp, unsigned char *payload);

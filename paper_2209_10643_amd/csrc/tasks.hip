@@ -128,7 +128,9 @@ extern "C" upir_status upir_taskwait(upir_ctx *c, int32_t mode) {
     for (auto &u : c->tasks)
       if (&t != &u && t.loop == u.loop && t.loop->has_red && t.loop->red.result_on_host)
         return upir_fail(c, UPIR_EINVAL, "a loop with a host-result reduction can back only one task per taskwait");
-  upir_status st = mode == UPIR_TASKWAIT_PLAIN ? run_plain(c) : upir_batched_run(c, false, nullptr);
+  upir_status st = settle(c);  // a deferred fold of an earlier loop runs before the tasks
+  if (st) return st;
+  st = mode == UPIR_TASKWAIT_PLAIN ? run_plain(c) : upir_batched_run(c, false, nullptr);
   if (st == UPIR_OK) st = deliver_task_results(c);
   clear_tasks(c);
   return st;
@@ -142,7 +144,8 @@ extern "C" upir_status upir_taskwait_graph(upir_ctx *c, int32_t mode, upir_graph
   for (auto &t : c->tasks)
     if (t.loop->has_red && t.loop->red.result_on_host)
       return upir_fail(c, UPIR_EINVAL, "graph-built tasks need device results");
-  upir_status st;
+  upir_status st = settle(c);
+  if (st) return st;
   if (mode == UPIR_TASKWAIT_BATCHED) {
     upir_graph_obj *g = nullptr;
     st = upir_batched_run(c, true, &g);

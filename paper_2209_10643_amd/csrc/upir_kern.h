@@ -44,6 +44,18 @@ struct SchedK {
   unsigned *dyn_exit;             // workgroups that finished claiming
 };
 
+// A reduction whose cross-workgroup fold was deferred: the partial values
+// (float64 or int64 bits) a finished kernel left behind, and where the
+// folded result goes. count == 0: nothing pending.
+struct FoldK {
+  const unsigned long long *part;
+  long long count;
+  int32_t op, is_int;
+  double init;
+  long long init_i;
+  void *result;
+};
+
 struct RedK {
   int32_t op;                 // RED_*
   int32_t is_int;             // accumulate exactly in int64
@@ -52,6 +64,8 @@ struct RedK {
   void *result;               // device double* or long long*
   unsigned long long *slots;  // two words per workgroup: value, flag
   long long spin_limit;       // bound on the combiner's wait per slot
+  unsigned long long *defer;  // non-null: leave one partial per wavefront here, fold later
+  FoldK fold;                 // an earlier loop's deferred fold, run by workgroup 0
 };
 
 // Empty float slot: all ones, a NaN that neither arithmetic nor a float32 to
@@ -359,12 +373,28 @@ __device__ inline void combine_slots(const RedK &R, T wg, T *lds) {
 __device__ inline void combine_f64(const RedK &R, double wg, double *lds) { combine_slots<double>(R, wg, lds); }
 __device__ inline void combine_i64(const RedK &R, long long wg, long long *lds) { combine_slots<long long>(R, wg, lds); }
 
+// Deferred finish: one partial per wavefront, stored at
+// defer[workgroup * wavefronts-per-workgroup + wavefront]; no cross-workgroup
+// traffic in this kernel.
+template <class T>
+__device__ inline void defer_partial(const RedK &R, T lane) {
+  const T w = wave_reduce(R.op, lane);
+  if (threadIdx.x % WAVE == 0) {
+    const int nw = (blockDim.x + WAVE - 1) / WAVE;
+    unsigned long long bits;
+    if constexpr (std::is_same<T, long long>::value) bits = (unsigned long long)w;
+    else bits = __builtin_bit_cast(unsigned long long, (double)w);
+    R.defer[(long long)blockIdx.x * nw + threadIdx.x / WAVE] = bits;
+  }
+}
+
 // Lane value -> workgroup value -> cross-workgroup combine.
 template <class A>
 __device__ inline void finish_reduction(const RedK &R, A lane);
 
 template <>
 __device__ inline void finish_reduction<float>(const RedK &R, float lane) {
+  if (R.defer) return defer_partial<float>(R, lane);
   __shared__ float lf[16];
   __shared__ double ld[16];
   float wg = block_reduce(R.op, lane, lf);
@@ -372,15 +402,45 @@ __device__ inline void finish_reduction<float>(const RedK &R, float lane) {
 }
 template <>
 __device__ inline void finish_reduction<double>(const RedK &R, double lane) {
+  if (R.defer) return defer_partial<double>(R, lane);
   __shared__ double ld[16];
   double wg = block_reduce(R.op, lane, ld);
   combine_f64(R, wg, ld);
 }
 template <>
 __device__ inline void finish_reduction<long long>(const RedK &R, long long lane) {
+  if (R.defer) return defer_partial<long long>(R, lane);
   __shared__ long long li[16];
   long long wg = block_reduce(R.op, lane, li);
   combine_i64(R, wg, li);
+}
+
+// Fold of a deferred reduction by one whole workgroup: thread t takes
+// partials t, t + U, ... in order, then a fixed tree; `init` is applied
+// once. The partials were written by an earlier kernel on the same stream,
+// so plain loads see them.
+__device__ inline void run_fold(const FoldK &F) {
+  __shared__ double fd[16];
+  __shared__ long long fi[16];
+  if (F.is_int) {
+    long long v = red_identity<long long>(F.op);
+    for (long long i = threadIdx.x; i < F.count; i += blockDim.x) v = red_apply(F.op, v, (long long)F.part[i]);
+    v = block_reduce(F.op, v, fi);
+    if (threadIdx.x == 0) *(long long *)F.result = red_apply(F.op, F.init_i, v);
+  } else {
+    double v = red_identity<double>(F.op);
+    for (long long i = threadIdx.x; i < F.count; i += blockDim.x)
+      v = red_apply(F.op, v, __builtin_bit_cast(double, F.part[i]));
+    v = block_reduce(F.op, v, fd);
+    if (threadIdx.x == 0) *(double *)F.result = red_apply(F.op, F.init, v);
+  }
+}
+
+// Called by every thread at the very end of a loop kernel: workgroup 0 runs
+// the fold an earlier loop deferred (after its own work, off the path of
+// the workgroups still running).
+__device__ inline void fold_hook(const RedK &R) {
+  if (R.fold.count > 0 && blockIdx.x == 0) run_fold(R.fold);
 }
 
 }  // namespace upir

@@ -34,6 +34,7 @@ hipError_t launch_generic(int32_t body, const void *payload, const LoopK &L, con
                           const RedK &R, hipStream_t st);
 hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, const SchedK &S,
                           const RedK &R, hipStream_t st);
+hipError_t launch_fold(const FoldK &F, hipStream_t st);
 hipError_t launch_jacobi_tile(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R,
                               hipStream_t st);
 hipError_t launch_matvec_wave(const MatvecP &p, const LoopK &L, const SchedK &S, const RedK &R,
