@@ -607,7 +607,7 @@ static std::vector<Cand> candidates(upir_ctx *c, const upir_loop_obj *lp) {
       }
       break;
     case UPIR_BODY_JACOBI5:
-      for (int th : {4, 8, 16, 32})
+      for (int th : {8, 16, 32, 64})
         for (int32_t U : {64, 128, 256, 512})
           if (U <= th * 64) add(0, U, UPIR_SCHED_STATIC, 0, th, 256);
       break;
@@ -694,7 +694,8 @@ static void features(const upir_loop_obj *lp, const Cand &k, float f[32]) {
   f[25] = (float)(lg((double)(k.sc.tile[0] > 0 ? k.sc.tile[0] : 1) * (k.sc.tile[1] > 0 ? k.sc.tile[1] : 1)) / 24);
   const double ws = n * bpi;
   f[26] = (float)(lg(ws / 256e6 + 1e-9) / 32);
-  f[27] = (kind == UPIR_BODY_JACOBI5 && k.sc.tile[0] > 0) ? (float)((k.sc.tile[0] + 2) * 264 * 4 / 163840.0) : 0.0f;
+  // Jacobi: rows of a wavefront's strip (tile rows / wavefronts per team)
+  f[27] = (kind == UPIR_BODY_JACOBI5 && k.sc.tile[0] > 0) ? (float)(k.sc.tile[0] / std::max(1.0, U / 64) / 64.0) : 0.0f;
   f[28] = (float)(lg(n * bpi) / 40);
   f[29] = (float)(lg(n * fpi + 1) / 48);
   f[30] = 0.0f;

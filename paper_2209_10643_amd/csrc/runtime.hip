@@ -640,8 +640,10 @@ void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sc
       }
       break;
     case UPIR_BODY_JACOBI5:
+      // tiles of 64 rows (16-row strips per wavefront) once the grid fills
+      // the chip with them, 16 rows below that
       sc.policy = UPIR_SCHED_STATIC;
-      sc.tile[0] = 16;
+      sc.tile[0] = lp->n >= (1LL << 22) ? 64 : 16;
       sc.tile[1] = 256;
       sp.num_teams = 0;  // one tile per team
       break;
@@ -815,10 +817,6 @@ upir_status resolve_plan(upir_ctx *c, const upir_spmd *spmd_in, upir_loop_obj *l
     if (resolve_payload(c, lp, pay) == UPIR_OK && matmul_mfma_supports(*(const MatmulP *)pay, L, S))
       v = V_MATMUL_MFMA;
     c->err.clear();
-  }
-  if (v == V_JACOBI_TILE) {
-    const size_t lds = (size_t)(S.tile[0] + 2) * (256 + 8) * 4;
-    if ((int)lds > c->max_lds) v = V_GENERIC;
   }
   pl.variant = v;
   pl.L = L;

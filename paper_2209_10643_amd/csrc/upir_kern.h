@@ -272,18 +272,24 @@ __device__ inline T block_reduce(int op, T v, T *lds) {
 
 // Device-coherent accesses. The XCDs' L2 caches are not coherent with each
 // other; atomic accesses at agent scope are performed at the device-coherent
-// level, so values published through them need no L2 write-back. A
-// workgroup-scope release fence waits until this thread's earlier accesses
-// have completed, which orders a published value before the counter update
-// that announces it (the agent-scope release fence would write back the
-// whole L2 of the XCD instead, about a microsecond per fence, serialised).
+// level, so values published through them need no L2 write-back.
+// complete_own_accesses() waits until this thread's earlier memory
+// operations have completed (a coherent store has then reached the
+// device-coherent level), which orders a published value before the counter
+// update that announces it. A workgroup-scope fence alone does not do this:
+// it emits no wait for global stores, because within one workgroup the
+// stores are already ordered. The agent-scope release fence would add a
+// write-back of the whole L2 of the XCD, about a microsecond per fence.
 __device__ inline void coh_store(unsigned long long *p, unsigned long long v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline unsigned long long coh_load(unsigned long long *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void complete_own_accesses() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup"); }
+__device__ inline void complete_own_accesses() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // no compiler reordering across this point
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");        // loads and stores of this thread complete
+}
 __device__ inline unsigned ticket_add(unsigned *t) {
   return __hip_atomic_fetch_add(t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
