@@ -62,6 +62,17 @@ class Timer:
 
 
 # ------------------------------------------------------------------ Jacobi
+# HBM traffic per 4096^2 sweep of k_jacobi_tile, keyed by (tile rows, units):
+# FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB copy), bytes,
+# from profiles/jacobi5_4096_hbm_traffic.md. Valid for the kernel as profiled.
+JACOBI_4096_TRAFFIC = {
+    (8, 64): 136573607, (8, 128): 135273284, (8, 256): 135312345, (8, 512): 135755561,
+    (16, 64): 143492386, (16, 128): 136346974, (16, 256): 135122245, (16, 512): 135281860,
+    (32, 64): 139630302, (32, 128): 143322352, (32, 256): 136678686, (32, 512): 135143642,
+    (64, 64): 137468424, (64, 128): 140208840, (64, 256): 143366284, (64, 512): 136320995,
+}
+
+
 class JacobiWork:
     N, SWEEPS = 4096, 100
 
@@ -574,7 +585,7 @@ def main():
     sweep_ms = timer.time(lambda: ctx.launch(jw.handles[0]), 200)
     ach = jw.bytes_per_sweep() / (sweep_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": JACOBI_4096_TRAFFIC.get((jw.tile[0], jw.units)),
                 "kernel": f"k_jacobi_tile<{jw.tile[0]},RED_MAX> ({jw.units} units, deferred fold)", "avg_launch_us": round(sweep_ms * 1e3, 3),
                 "algorithmic_bytes_per_launch": jw.bytes_per_sweep()}
     res = jw.res.cpu().numpy()
