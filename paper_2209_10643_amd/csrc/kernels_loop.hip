@@ -208,18 +208,35 @@ hipError_t launch_generic(int32_t body, const void *payload, const LoopK &L, con
 // Ownership: chunk m (4 iterations) belongs to flat unit m mod (T U), flat =
 // team U + unit, exactly the static-chunk-4 schedule. x and y point at the
 // element of the first iteration and are 16-byte aligned. Four owned chunks
-// are loaded before any is used to keep several loads in flight.
-template <int BODY, bool RED>
+// of each input (eight for SUM) are loaded before any is used to keep
+// several loads in flight. NT: the
+// arrays are larger than the last-level cache, so loads and stores carry the
+// non-temporal hint (streamed through, not kept).
+template <bool NT>
+__device__ __forceinline__ f32x4 ld4(const f32x4 *p) {
+  if (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st4(f32x4 *p, f32x4 v) {
+  if (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// OP is the reduction (RED_NONE for none), fixed at compile time so the
+// per-element fold is one instruction.
+template <int BODY, int OP, bool NT>
 __global__ void __launch_bounds__(1024) k_stream4(int64_t n, float a, const float *__restrict__ x,
                                                   float *__restrict__ y, int32_t *__restrict__ cnt, RedK R) {
+  constexpr bool RED = OP != RED_NONE;
   const int64_t F = (int64_t)gridDim.x * blockDim.x;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nc = n >> 2;
-  float acc = RED ? red_identity<float>(R.op) : 0.0f;
+  float acc = RED ? red_identity<float>(OP) : 0.0f;
   const f32x4 *x4 = (const f32x4 *)x;
   f32x4 *y4 = (f32x4 *)y;
   auto fold = [&](float v) {
-    if (RED) acc = red_apply(R.op, acc, v);
+    if (RED) acc = red_apply(OP, acc, v);
   };
   int64_t m = f;
   if (BODY == 1) {  // AXPY
@@ -227,8 +244,8 @@ __global__ void __launch_bounds__(1024) k_stream4(int64_t n, float a, const floa
       f32x4 xv[4], yv[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        xv[u] = x4[m + u * F];
-        yv[u] = y4[m + u * F];
+        xv[u] = ld4<NT>(&x4[m + u * F]);
+        yv[u] = ld4<NT>(&y4[m + u * F]);
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -237,7 +254,7 @@ __global__ void __launch_bounds__(1024) k_stream4(int64_t n, float a, const floa
         r.y = __builtin_fmaf(a, xv[u].y, yv[u].y);
         r.z = __builtin_fmaf(a, xv[u].z, yv[u].z);
         r.w = __builtin_fmaf(a, xv[u].w, yv[u].w);
-        y4[m + u * F] = r;
+        st4<NT>(&y4[m + u * F], r);
         fold(r.x); fold(r.y); fold(r.z); fold(r.w);
       }
     }
@@ -258,13 +275,13 @@ __global__ void __launch_bounds__(1024) k_stream4(int64_t n, float a, const floa
         fold(r);
       }
     }
-  } else if (BODY == 2) {  // SUM over float32
-    for (; m + 3 * F < nc; m += 4 * F) {
-      f32x4 xv[4];
+  } else if (BODY == 2) {  // SUM over float32: eight chunks in flight (one input stream)
+    for (; m + 7 * F < nc; m += 8 * F) {
+      f32x4 xv[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) xv[u] = x4[m + u * F];
+      for (int u = 0; u < 8; ++u) xv[u] = ld4<NT>(&x4[m + u * F]);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) { fold(xv[u].x); fold(xv[u].y); fold(xv[u].z); fold(xv[u].w); }
+      for (int u = 0; u < 8; ++u) { fold(xv[u].x); fold(xv[u].y); fold(xv[u].z); fold(xv[u].w); }
     }
     for (; m < nc; m += F) {
       f32x4 xv = x4[m];
@@ -284,25 +301,43 @@ __global__ void __launch_bounds__(1024) k_stream4(int64_t n, float a, const floa
   fold_hook(R);
 }
 
+template <int BODY, int OP>
+static void go_stream4(bool nt, dim3 g, dim3 b, hipStream_t st, int64_t n, float a, const float *x, float *y,
+                       int32_t *cnt, const RedK &R) {
+  if (nt)
+    hipLaunchKernelGGL((k_stream4<BODY, OP, true>), g, b, 0, st, n, a, x, y, cnt, R);
+  else
+    hipLaunchKernelGGL((k_stream4<BODY, OP, false>), g, b, 0, st, n, a, x, y, cnt, R);
+}
+
+template <int BODY>
+static void go_stream4_op(bool nt, dim3 g, dim3 b, hipStream_t st, int64_t n, float a, const float *x, float *y,
+                          int32_t *cnt, const RedK &R) {
+  switch (R.op) {
+    case RED_SUM: return go_stream4<BODY, RED_SUM>(nt, g, b, st, n, a, x, y, cnt, R);
+    case RED_MAX: return go_stream4<BODY, RED_MAX>(nt, g, b, st, n, a, x, y, cnt, R);
+    case RED_MIN: return go_stream4<BODY, RED_MIN>(nt, g, b, st, n, a, x, y, cnt, R);
+    default: return go_stream4<BODY, RED_NONE>(nt, g, b, st, n, a, x, y, cnt, R);
+  }
+}
+
 hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, const SchedK &S, const RedK &R,
                           hipStream_t st) {
-  const bool red = R.op != RED_NONE;
+  // beyond the 256 MB last-level cache the arrays cannot stay resident
+  const bool nt = (uint64_t)L.n * (body == 1 ? 8u : 4u) > (256ull << 20);
   const int64_t n = L.n, lb = L.lb[0];
   dim3 g(S.T), b(S.U);
   if (body == 1) {
     const AxpyP &p = *(const AxpyP *)payload;
-    if (red)
-      hipLaunchKernelGGL((k_stream4<1, true>), g, b, 0, st, n, p.a, p.x + lb, p.y + lb, (int32_t *)nullptr, R);
-    else
-      hipLaunchKernelGGL((k_stream4<1, false>), g, b, 0, st, n, p.a, p.x + lb, p.y + lb, (int32_t *)nullptr, R);
+    go_stream4_op<1>(nt, g, b, st, n, p.a, p.x + lb, p.y + lb, nullptr, R);
   } else if (body == 2) {
+    if (R.op == RED_NONE) return hipErrorInvalidValue;
     const SumP &p = *(const SumP *)payload;
-    hipLaunchKernelGGL((k_stream4<2, true>), g, b, 0, st, n, 0.0f, (const float *)p.x + lb, (float *)nullptr,
-                       (int32_t *)nullptr, R);
+    go_stream4_op<2>(nt, g, b, st, n, 0.0f, (const float *)p.x + lb, nullptr, nullptr, R);
   } else if (body == 9) {
     const CoverP &p = *(const CoverP *)payload;
-    hipLaunchKernelGGL((k_stream4<9, false>), g, b, 0, st, n, 0.0f, (const float *)nullptr, (float *)nullptr,
-                       p.count, R);
+    hipLaunchKernelGGL((k_stream4<9, RED_NONE, false>), g, b, 0, st, n, 0.0f, (const float *)nullptr,
+                       (float *)nullptr, p.count, R);
   } else {
     return hipErrorInvalidValue;
   }

@@ -601,6 +601,8 @@ static std::vector<Cand> candidates(upir_ctx *c, const upir_loop_obj *lp) {
       if (lp->loop.collapse == 1 && (lp->kind != UPIR_BODY_SUM || lp->sum_dtype == UPIR_DT_F32)) {
         for (int32_t U : {64, 256, 1024})
           for (int64_t per : {4, 16, 64, 256}) add(teams(n, U * per), U, UPIR_SCHED_STATIC_CHUNK, 4);
+        for (int32_t U : {256, 512})  // one team per CU
+          add((int32_t)std::min<int64_t>(c->num_cus, teams(n, U * 4)), U, UPIR_SCHED_STATIC_CHUNK, 4);
       } else {
         for (int32_t U : {64, 256, 1024})
           for (int64_t per : {1, 8, 64}) add(teams(n, U * per), U, UPIR_SCHED_STATIC, 0);

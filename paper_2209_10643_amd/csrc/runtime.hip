@@ -631,9 +631,11 @@ void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sc
     case UPIR_BODY_COVER:
     case UPIR_BODY_SUM:
       if (lp->loop.collapse == 1) {
+        // one 256-unit team per CU at most: fewer, longer streams keep HBM
+        // pages open better than many short ones
         sc.policy = UPIR_SCHED_STATIC_CHUNK;
         sc.chunk = 4;
-        sp.num_teams = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 16LL * 256), cap));
+        sp.num_teams = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 16LL * 256), c->num_cus));
       } else {
         sc.policy = UPIR_SCHED_STATIC;
         sp.num_teams = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 8LL * 256), cap));

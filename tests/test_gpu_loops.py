@@ -82,6 +82,29 @@ def test_axpy_sum_parity(ctx, n, sched, spmd):
     assert abs(got_s - want_s) <= 1e-5 * bodies.sum_abs_f64(want_y)
 
 
+def test_stream_beyond_last_level_cache(ctx):
+    """Arrays larger than the 256 MB last-level cache take the non-temporal
+    streaming kernel: AXPY + sum at n = 40M + 3, SUM body at n = 70M + 1."""
+    n = 40_000_003
+    x, y = synth.uniform_pm1(21, 0, n), synth.uniform_pm1(21, 1, n)
+    got_y, got_s, v = run_axpy(ctx, x, y, 2.5, [(0, n, 1)])
+    assert U.VARIANTS[v] == "stream4"
+    want_y = bodies.axpy(2.5, x, y)
+    assert np.array_equal(got_y, want_y)
+    assert abs(got_s - bodies.sum_f64(want_y)) <= 1e-5 * bodies.sum_abs_f64(want_y)
+    del x, y, got_y, want_y
+    m = 70_000_001
+    z = synth.uniform_pm1(22, 0, m)
+    tz, r = dev(z), dbl()
+    lp = ctx.loop(U.UPIR_BODY_SUM, U.upir_sum_args(tz.data_ptr(), U.UPIR_DT_F32, 0), [(0, m, 1)], None,
+                  H.make_red(U.UPIR_RED_SUM, r.data_ptr()))
+    assert U.VARIANTS[ctx.resolve(lp)[2]] == "stream4"
+    ctx.launch(lp)
+    ctx.sync()
+    assert abs(r.item() - bodies.sum_f64(z)) <= 1e-5 * bodies.sum_abs_f64(z)
+    ctx.free(lp)
+
+
 def test_axpy_default_uses_vector_path(ctx):
     n = 2 ** 20
     x, y = synth.uniform_pm1(1, 0, n), synth.uniform_pm1(1, 1, n)
