@@ -434,7 +434,7 @@ __device__ __forceinline__ void jacobi_strip(const JacobiP &p, int64_t ra, int64
       v.w = ((up.w + S.w) + (mid.z + Ep)) * 0.25f;
       float *out = p.dst + (r + q) * ld + c0;
       if (!EDGE || (c0 >= jlo && c0 + 3 < jhi)) {
-        *(f32x4 *)out = v;
+        __builtin_nontemporal_store(v, (f32x4 *)out);  // read back only by the next sweep
         if (RED) {
           acc.add(v.x, mid.x);
           acc.add(v.y, mid.y);
