@@ -137,6 +137,29 @@ def jacobi5(u0: np.ndarray, sweeps: int, mode: str = "f32", op: str = "max"):
     return u, np.array(res, dtype=np.float64)
 
 
+def filter7(src: np.ndarray, w: np.ndarray, dst: np.ndarray = None) -> np.ndarray:
+    """2-D stencil with a 7 x 7 filter (sec. 6, the stencil of "filter size 7").
+
+    For every point at distance >= 3 from the edge,
+    ``out[i, j] = sum over m, n in 0..6 of w[m, n] * src[i + m - 3, j + n - 3]``,
+    accumulated in float32 by fused multiply-adds in the order m = 0..6 (outer),
+    n = 0..6 (inner), starting from 0. Points within 3 of the edge keep the
+    value of ``dst`` (of ``src`` when ``dst`` is None).
+    """
+    src = np.asarray(src, dtype=np.float32)
+    w = np.asarray(w, dtype=np.float32).reshape(7, 7)
+    out = np.array(src if dst is None else dst, dtype=np.float32, copy=True)
+    H, W = src.shape
+    if H < 7 or W < 7:
+        return out
+    s = np.zeros((H - 6, W - 6), dtype=np.float32)
+    for m in range(7):
+        for n in range(7):
+            s = fma_f32(w[m, n], src[m:m + H - 6, n:n + W - 6], s)
+    out[3:-3, 3:-3] = s
+    return out
+
+
 # --------------------------------------------------------------------------
 # matvec and matmul (sec. 6.2 names them; definitions written out)
 # --------------------------------------------------------------------------

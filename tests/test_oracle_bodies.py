@@ -179,6 +179,52 @@ def test_jacobi_eigenmode_decay_f64():
     assert np.abs(got - lam ** k * u).max() < 1e-12
 
 
+# ------------------------------------------------------------- filter7 ----
+
+def test_filter7_brute_force_exact_rationals():
+    """Every interior point: 49 fused multiply-adds in filter order, each the
+    exact rational a*x + s rounded once to float32."""
+    H, W = 9, 11
+    src = synth.uniform_pm1(30, 0, H * W).reshape(H, W)
+    w = synth.uniform_pm1(30, 1, 49).reshape(7, 7)
+    dst0 = synth.uniform_pm1(30, 2, H * W).reshape(H, W)
+    got = bodies.filter7(src, w, dst0)
+    for i in range(H):
+        for j in range(W):
+            if 3 <= i < H - 3 and 3 <= j < W - 3:
+                acc = np.float32(0)
+                for m in range(7):
+                    for n in range(7):
+                        acc = _rn32_exact(F(float(w[m, n])) * F(float(src[i + m - 3, j + n - 3])) + F(float(acc)))
+                assert got[i, j] == acc, (i, j)
+            else:
+                assert got[i, j] == dst0[i, j], (i, j)
+
+
+def test_filter7_delta_shift_and_constant():
+    H, W = 20, 23
+    src = synth.uniform_pm1(31, 0, H * W).reshape(H, W)
+    delta = np.zeros((7, 7), np.float32)
+    delta[3, 3] = 1
+    assert np.array_equal(bodies.filter7(src, delta), src)          # identity
+    shift = np.zeros((7, 7), np.float32)
+    shift[1, 5] = 1                                                   # row -2, column +2
+    got = bodies.filter7(src, shift)
+    assert np.array_equal(got[3:-3, 3:-3], src[1:-5, 5:-1])
+    # constant field, weights on the 2^-6 grid: every partial sum is exact
+    w = np.round(synth.uniform_pm1(31, 1, 49) * 64).astype(np.float32).reshape(7, 7) / 64
+    c = np.float32(0.75)
+    got = bodies.filter7(np.full((H, W), c, np.float32), w)
+    total = sum(F(float(v)) for v in w.ravel()) * F(float(c))
+    assert (got[3:-3, 3:-3] == np.float32(float(total))).all()
+
+
+def test_filter7_small_arrays_unchanged():
+    for H, W in [(6, 9), (9, 6), (1, 1)]:
+        a = synth.uniform_pm1(32, 0, H * W).reshape(H, W)
+        assert np.array_equal(bodies.filter7(a, np.ones((7, 7), np.float32)), a)
+
+
 # -------------------------------------------------------------- matmul ----
 
 def test_matmul_integer_brute_force():
