@@ -191,6 +191,12 @@ typedef struct {
                                       the unit is a 64-lane wavefront */
 #define UPIR_BODY_OWNER         8  /* any: out[k] = team * U + unit of iteration k */
 #define UPIR_BODY_COVER         9  /* any: count[k] += 1 (atomic) */
+#define UPIR_BODY_FILTER7      10  /* 2-D (sec. 6 stencil, filter size 7):
+                                      dst[i][j] = sum_{m,n<7} w[m][n] *
+                                      src[i+m-3][j+n-3], float32 fma chain with
+                                      m outer, n inner, from 0; no reduction.
+                                      The loop box must keep the reads inside
+                                      the array (lb >= 3, ub <= extent - 3). */
 
 typedef struct { float a; int32_t pad_; const float *x; float *y; } upir_axpy_args;
 typedef struct { const void *x; int32_t dtype; int32_t pad_; } upir_sum_args;    /* dtype UPIR_DT_* */
@@ -204,6 +210,9 @@ typedef struct {
 typedef struct { const float *A; const float *x; float *y; int64_t cols, lda; } upir_matvec_args;
 typedef struct { int32_t *out; } upir_owner_args;
 typedef struct { int32_t *count; } upir_cover_args;
+typedef struct { const float *src; float *dst; const float *w; int64_t ld; } upir_filter7_args;
+                                   /* w: 49 float32 weights, row-major 7 x 7;
+                                      src and dst row-major with pitch ld, distinct */
 #define UPIR_DT_F32 1
 #define UPIR_DT_F64 2
 #define UPIR_DT_I32 3

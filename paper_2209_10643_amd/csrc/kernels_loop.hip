@@ -81,6 +81,19 @@ struct BMatmul {
   }
 };
 
+// 7 x 7 filter, one point: the fused multiply-add chain of the definition.
+struct BFilter7 {
+  using Acc = float;
+  Filter7P p;
+  __device__ void operator()(int64_t, const int64_t *iv, int, int, Acc &, int) const {
+    const int64_t i = iv[0], j = iv[1], ld = p.ld;
+    float s = 0.0f;
+    for (int m = 0; m < 7; ++m)
+      for (int n = 0; n < 7; ++n) s = __builtin_fmaf(p.w[m * 7 + n], p.src[(i + m - 3) * ld + j + n - 3], s);
+    p.dst[i * ld + j] = s;
+  }
+};
+
 struct BOwner {
   using Acc = float;
   OwnerP p;
@@ -200,6 +213,7 @@ hipError_t launch_generic(int32_t body, const void *payload, const LoopK &L, con
     case 6: return go_generic(BMatmul{*(const MatmulP *)payload}, L, S, R, st);
     case 8: return go_generic(BOwner{*(const OwnerP *)payload, S.U}, L, S, R, st);
     case 9: return go_generic(BCover{*(const CoverP *)payload}, L, S, R, st);
+    case 10: return go_generic(BFilter7{*(const Filter7P *)payload}, L, S, R, st);
   }
   return hipErrorInvalidValue;
 }
@@ -530,6 +544,167 @@ hipError_t launch_jacobi_tile(const JacobiP &p, const LoopK &L, const SchedK &S,
     case 64: return go_jacobi<64>(p, L, S, R, st);
   }
   return hipErrorInvalidValue;
+}
+
+// ----------------------------------------- 7 x 7 filter, wavefront strips
+// Tiles of TH rows x 256 columns go to teams as for Jacobi; wavefront w of a
+// team takes a strip of ceil(TH / NW) rows and lane l columns 4l .. 4l+3.
+// The wavefront walks the input rows from three above its strip to three
+// below. Each input row is assembled as ten values per lane (columns
+// 4l-3 .. 4l+6: its own four and three from each neighbouring lane; lanes 0
+// and 63 load the tile's halo) and added into the seven output rows it
+// feeds. An output row receives filter row m = 0..6 in that order, and
+// within a row n = 0..6, so its value is the definition's fused
+// multiply-add chain. After each input row the oldest output row is
+// complete and is stored.
+constexpr int F7_G = 4;  // input rows loaded together
+
+struct F7Row {
+  f32x4 v;
+  float h0, h1, h2;  // lane 0: columns c0-3 .. c0-1; lane 63: columns c0+4 .. c0+6
+};
+
+template <bool EDGE>
+__device__ __forceinline__ void f7_load(const float *row, int64_t c0, int lane, int64_t clo, int64_t chi, F7Row &r) {
+  if (!EDGE || (c0 >= clo && c0 + 3 <= chi)) {
+    r.v = *(const f32x4 *)(row + c0);
+  } else {
+    float e[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) e[q] = (c0 + q >= clo && c0 + q <= chi) ? row[c0 + q] : 0.0f;
+    r.v = f32x4{e[0], e[1], e[2], e[3]};
+  }
+  r.h0 = r.h1 = r.h2 = 0.0f;
+  if (lane == 0) {
+    if (c0 - 3 >= clo) r.h0 = row[c0 - 3];
+    if (c0 - 2 >= clo) r.h1 = row[c0 - 2];
+    if (c0 - 1 >= clo) r.h2 = row[c0 - 1];
+  } else if (lane == WAVE - 1) {
+    if (c0 + 4 <= chi) r.h0 = row[c0 + 4];
+    if (c0 + 5 <= chi) r.h1 = row[c0 + 5];
+    if (c0 + 6 <= chi) r.h2 = row[c0 + 6];
+  }
+}
+
+template <bool EDGE>
+__device__ __forceinline__ void f7_strip(const Filter7P &p, const float (&wk)[49], int64_t ra, int64_t rb, int64_t c0,
+                                         int lane, int64_t clo, int64_t chi, int64_t jlo, int64_t jhi) {
+  const int64_t ld = p.ld;
+  float acc[7][4];  // acc[k]: output row (input row - 3 + k), which takes filter row 6 - k next
+#pragma unroll
+  for (int k = 0; k < 7; ++k)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[k][q] = 0.0f;
+  const int64_t rlast = rb + 2;  // last input row
+  for (int64_t r0 = ra - 3; r0 <= rlast; r0 += F7_G) {
+    F7Row in[F7_G];
+#pragma unroll
+    for (int g = 0; g < F7_G; ++g) {
+      const int64_t rr = r0 + g < rlast ? r0 + g : rlast;
+      f7_load<EDGE>(p.src + rr * ld, c0, lane, clo, chi, in[g]);
+    }
+#pragma unroll
+    for (int g = 0; g < F7_G; ++g) {
+      const int64_t r = r0 + g;
+      if (r > rlast) break;
+      const F7Row &x = in[g];
+      const float l1 = __shfl_up(x.v.y, 1), l2 = __shfl_up(x.v.z, 1), l3 = __shfl_up(x.v.w, 1);
+      const float q1 = __shfl_down(x.v.x, 1), q2 = __shfl_down(x.v.y, 1), q3 = __shfl_down(x.v.z, 1);
+      const bool first = lane == 0, last = lane == WAVE - 1;
+      const float seg[10] = {first ? x.h0 : l1, first ? x.h1 : l2, first ? x.h2 : l3, x.v.x, x.v.y, x.v.z, x.v.w,
+                             last ? x.h0 : q1,  last ? x.h1 : q2,  last ? x.h2 : q3};
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const int64_t o = r - 3 + k;
+        if (o >= ra && o < rb) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int n = 0; n < 7; ++n) acc[k][q] = __builtin_fmaf(wk[(6 - k) * 7 + n], seg[q + n], acc[k][q]);
+        }
+      }
+      const int64_t o = r - 3;  // complete: it has taken filter row 6
+      if (o >= ra && o < rb) {
+        float *out = p.dst + o * ld + c0;
+        if (!EDGE || (c0 >= jlo && c0 + 3 < jhi)) {
+          __builtin_nontemporal_store(f32x4{acc[0][0], acc[0][1], acc[0][2], acc[0][3]}, (f32x4 *)out);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (c0 + q >= jlo && c0 + q < jhi) out[q] = acc[0][q];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[k][q] = acc[k + 1][q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[6][q] = 0.0f;
+    }
+  }
+}
+
+template <int TH>
+__global__ void __launch_bounds__(1024) k_filter7_tile(LoopK L, SchedK S, Filter7P p, RedK R) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, NW = blockDim.x / WAVE;
+  const int team = xcd_team(blockIdx.x, gridDim.x);
+  const int SH = (TH + NW - 1) / NW;
+  const int64_t ilo = L.lb[0], ihi = L.lb[0] + L.cnt[0];
+  const int64_t jlo = L.lb[1], jhi = L.lb[1] + L.cnt[1];
+  float wk[49];
+#pragma unroll
+  for (int i = 0; i < 49; ++i) wk[i] = p.w[i];
+  auto do_tile = [&](int64_t m) {
+    const int64_t ti = S.t0[0] + m / S.nt[1], tj = S.t0[1] + m % S.nt[1];
+    const int64_t i0 = ti * TH, j0 = tj * JT_W;
+    const int64_t s0 = i0 + (int64_t)w * SH, s1 = s0 + SH < i0 + TH ? s0 + SH : i0 + TH;
+    const int64_t ra = s0 > ilo ? s0 : ilo, rb = s1 < ihi ? s1 : ihi;
+    if (ra >= rb) return;
+    const int64_t c0 = j0 + 4 * lane;
+    if (j0 >= jlo && j0 + JT_W <= jhi) {
+      f7_strip<false>(p, wk, ra, rb, c0, lane, j0 - 3, j0 + JT_W + 2, jlo, jhi);
+    } else {
+      // columns read by in-box points of this tile (inclusive)
+      const int64_t clo = (j0 > jlo ? j0 : jlo) - 3, chi = (j0 + JT_W < jhi ? j0 + JT_W : jhi) + 2;
+      f7_strip<true>(p, wk, ra, rb, c0, lane, clo, chi, jlo, jhi);
+    }
+  };
+  if (S.policy == POL_STATIC) {
+    int64_t lo, hi;
+    block_range(S.ntiles, S.T, team, lo, hi);
+    for (int64_t m = lo; m < hi; ++m) do_tile(m);
+  } else {
+    const int64_t c = S.chunk;
+    for (int64_t m0 = (int64_t)team * c; m0 < S.ntiles; m0 += (int64_t)S.T * c)
+      for (int64_t m = m0; m < m0 + c && m < S.ntiles; ++m) do_tile(m);
+  }
+  fold_hook(R);
+}
+
+bool filter7_tile_supports(const Filter7P &p, const LoopK &L, const SchedK &S) {
+  if (L.nd != 2 || !S.tiled || S.dist != DIST_TU) return false;
+  if (L.step[0] != 1 || L.step[1] != 1) return false;
+  if (S.tile[1] != JT_W) return false;
+  const int th = S.tile[0];
+  if (th != 4 && th != 8 && th != 16 && th != 32 && th != 64) return false;
+  if (S.U % WAVE != 0 || S.U < WAVE) return false;
+  if (S.policy != POL_STATIC && S.policy != POL_CHUNK) return false;
+  if ((p.ld % 4) != 0 || ((uintptr_t)p.src % 16) != 0 || ((uintptr_t)p.dst % 16) != 0) return false;
+  if (L.lb[1] < 3 || L.lb[0] < 3) return false;  // reads at lb-3 stay in the array
+  return true;
+}
+
+hipError_t launch_filter7_tile(const Filter7P &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
+  const dim3 g(S.T), b(S.U);
+  switch (S.tile[0]) {
+    case 4: hipLaunchKernelGGL(k_filter7_tile<4>, g, b, 0, st, L, S, p, R); break;
+    case 8: hipLaunchKernelGGL(k_filter7_tile<8>, g, b, 0, st, L, S, p, R); break;
+    case 16: hipLaunchKernelGGL(k_filter7_tile<16>, g, b, 0, st, L, S, p, R); break;
+    case 32: hipLaunchKernelGGL(k_filter7_tile<32>, g, b, 0, st, L, S, p, R); break;
+    case 64: hipLaunchKernelGGL(k_filter7_tile<64>, g, b, 0, st, L, S, p, R); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------- matvec, wave/row

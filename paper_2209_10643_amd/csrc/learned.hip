@@ -609,6 +609,7 @@ static std::vector<Cand> candidates(upir_ctx *c, const upir_loop_obj *lp) {
       }
       break;
     case UPIR_BODY_JACOBI5:
+    case UPIR_BODY_FILTER7:
       for (int th : {8, 16, 32, 64})
         for (int32_t U : {64, 128, 256, 512})
           if (U <= th * 64) add(0, U, UPIR_SCHED_STATIC, 0, th, 256);
@@ -648,7 +649,7 @@ static void features(const upir_loop_obj *lp, const Cand &k, float f[32]) {
   const int kind = lp->kind;
   const int cls = kind == UPIR_BODY_AXPY || kind == UPIR_BODY_COVER ? 0
                   : kind == UPIR_BODY_SUM                           ? 1
-                  : kind == UPIR_BODY_JACOBI5                       ? 2
+                  : kind == UPIR_BODY_JACOBI5 || kind == UPIR_BODY_FILTER7 ? 2
                   : kind == UPIR_BODY_MATVEC                        ? 3
                                                                     : 4;
   f[cls] = 1.0f;
@@ -658,6 +659,7 @@ static void features(const upir_loop_obj *lp, const Cand &k, float f[32]) {
   if (kind == UPIR_BODY_SUM) bpi = 4, fpi = 1;
   if (kind == UPIR_BODY_COVER) bpi = 8, fpi = 0;
   if (kind == UPIR_BODY_JACOBI5) bpi = 8, fpi = 7;
+  if (kind == UPIR_BODY_FILTER7) bpi = 8, fpi = 98;
   if (kind == UPIR_BODY_MATVEC) {
     cols = (double)((const upir_matvec_args *)lp->args)->cols;
     bpi = 4 * cols + 4, fpi = 2 * cols;
@@ -697,7 +699,7 @@ static void features(const upir_loop_obj *lp, const Cand &k, float f[32]) {
   const double ws = n * bpi;
   f[26] = (float)(lg(ws / 256e6 + 1e-9) / 32);
   // Jacobi: rows of a wavefront's strip (tile rows / wavefronts per team)
-  f[27] = (kind == UPIR_BODY_JACOBI5 && k.sc.tile[0] > 0) ? (float)(k.sc.tile[0] / std::max(1.0, U / 64) / 64.0) : 0.0f;
+  f[27] = ((kind == UPIR_BODY_JACOBI5 || kind == UPIR_BODY_FILTER7) && k.sc.tile[0] > 0) ? (float)(k.sc.tile[0] / std::max(1.0, U / 64) / 64.0) : 0.0f;
   f[28] = (float)(lg(n * bpi) / 40);
   f[29] = (float)(lg(n * fpi + 1) / 48);
   f[30] = 0.0f;
@@ -854,6 +856,15 @@ extern "C" upir_status upir_tune(upir_ctx *c, const upir_spmd *spmd, upir_loop_h
       float *d2 = (float *)own((size_t)rows * p.ld * 4);
       if (!d2) break;
       upir_jacobi5_args a{p.src, d2, p.ld};
+      memcpy(tmp.args, &a, sizeof a);
+      break;
+    }
+    case UPIR_BODY_FILTER7: {  // dst on a scratch grid of the same pitch
+      const Filter7P &p = *(const Filter7P *)pay;
+      const int64_t rows = lp->loop.dim[0].lb + lp->cnt[0] + 3;
+      float *d2 = (float *)own((size_t)rows * p.ld * 4);
+      if (!d2) break;
+      upir_filter7_args a{p.src, d2, p.w, p.ld};
       memcpy(tmp.args, &a, sizeof a);
       break;
     }

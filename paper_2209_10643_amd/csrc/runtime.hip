@@ -310,6 +310,7 @@ static size_t args_size_of(int32_t kind) {
     case UPIR_BODY_MATVEC: return sizeof(upir_matvec_args);
     case UPIR_BODY_OWNER: return sizeof(upir_owner_args);
     case UPIR_BODY_COVER: return sizeof(upir_cover_args);
+    case UPIR_BODY_FILTER7: return sizeof(upir_filter7_args);
   }
   return 0;
 }
@@ -381,7 +382,7 @@ extern "C" upir_status upir_loop_parallel(upir_ctx *c, const upir_loop *loop, co
     return upir_fail(c, UPIR_EINVAL, "body args size %zu, expected %zu", body->args_size, asz);
   if ((kind == UPIR_BODY_AXPY || kind == UPIR_BODY_SUM || kind == UPIR_BODY_MATVEC) && L.collapse != 1)
     return upir_fail(c, UPIR_EINVAL, "this body runs a 1-D loop");
-  if ((kind == UPIR_BODY_JACOBI5 || is_matmul(kind)) && L.collapse != 2)
+  if ((kind == UPIR_BODY_JACOBI5 || kind == UPIR_BODY_FILTER7 || is_matmul(kind)) && L.collapse != 2)
     return upir_fail(c, UPIR_EINVAL, "this body runs a collapse(2) loop");
   upir_sched S{};
   S.policy = UPIR_SCHED_AUTO;
@@ -393,7 +394,7 @@ extern "C" upir_status upir_loop_parallel(upir_ctx *c, const upir_loop *loop, co
   if (red) R = *red;
   if (red && (red->op < UPIR_RED_NONE || red->op > UPIR_RED_MIN)) return upir_fail(c, UPIR_EINVAL, "reduction op");
   if (kind == UPIR_BODY_SUM && !has_red) return upir_fail(c, UPIR_EINVAL, "SUM body needs a reduction");
-  if (has_red && (is_matmul(kind) || kind == UPIR_BODY_OWNER || kind == UPIR_BODY_COVER))
+  if (has_red && (is_matmul(kind) || kind == UPIR_BODY_OWNER || kind == UPIR_BODY_COVER || kind == UPIR_BODY_FILTER7))
     return upir_fail(c, UPIR_EINVAL, "this body has no value to reduce");
   if (has_red && !R.result) return upir_fail(c, UPIR_EINVAL, "reduction without a result address");
   int32_t sum_dtype = UPIR_DT_F32;
@@ -421,6 +422,8 @@ extern "C" upir_status upir_loop_parallel(upir_ctx *c, const upir_loop *loop, co
   }
   if (kind == UPIR_BODY_JACOBI5 && ((const upir_jacobi5_args *)body->args)->ld < 1)
     return upir_fail(c, UPIR_EINVAL, "jacobi leading dimension");
+  if (kind == UPIR_BODY_FILTER7 && ((const upir_filter7_args *)body->args)->ld < 1)
+    return upir_fail(c, UPIR_EINVAL, "filter leading dimension");
   if (has_red && R.result_on_host && c->none) return upir_fail(c, UPIR_ESTATE, "host results need a device");
 
   upir_loop_obj *lp = new (std::nothrow) upir_loop_obj();
@@ -556,6 +559,16 @@ upir_status resolve_payload(upir_ctx *c, upir_loop_obj *lp, unsigned char *paylo
       memcpy(payload, &p, sizeof p);
       break;
     }
+    case UPIR_BODY_FILTER7: {
+      const upir_filter7_args &a = *(const upir_filter7_args *)lp->args;
+      const void *s, *d, *w;
+      if ((st = xlate(c, lp, a.src, &s)) || (st = xlate(c, lp, a.dst, &d)) || (st = xlate(c, lp, a.w, &w))) return st;
+      if (lp->n > 0 && (!s || !d || !w)) return upir_fail(c, UPIR_EINVAL, "FILTER7 needs src, dst and w");
+      if (lp->n > 0 && s == d) return upir_fail(c, UPIR_EINVAL, "FILTER7 src and dst must differ");
+      Filter7P p{(const float *)s, (float *)d, (const float *)w, a.ld};
+      memcpy(payload, &p, sizeof p);
+      break;
+    }
     case UPIR_BODY_MATMUL_F32:
     case UPIR_BODY_MATMUL_BF16:
     case UPIR_BODY_MATMUL_SPLIT3: {
@@ -648,6 +661,14 @@ void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sc
       sc.tile[0] = lp->n >= (1LL << 22) ? 64 : 16;
       sc.tile[1] = 256;
       sp.num_teams = 0;  // one tile per team
+      break;
+    case UPIR_BODY_FILTER7:
+      // 7 x 7 filter: strips of 16 rows per wavefront on large grids (each
+      // input row feeds seven output rows), 4 rows on small ones
+      sc.policy = UPIR_SCHED_STATIC;
+      sc.tile[0] = lp->n >= (1LL << 20) ? 64 : 16;
+      sc.tile[1] = 256;
+      sp.num_teams = 0;
       break;
     case UPIR_BODY_MATMUL_F32:
     case UPIR_BODY_MATMUL_BF16:
@@ -767,7 +788,7 @@ upir_status resolve_plan(upir_ctx *c, const upir_spmd *spmd_in, upir_loop_obj *l
   if (T == 0) {
     if (S.tiled) {
       T = S.policy == UPIR_SCHED_STATIC ? S.ntiles : cdiv(S.ntiles, S.chunk);
-      if (is_matmul(lp->kind) || lp->kind == UPIR_BODY_JACOBI5) T = std::max<int64_t>(T, 1);
+      if (is_matmul(lp->kind) || lp->kind == UPIR_BODY_JACOBI5 || lp->kind == UPIR_BODY_FILTER7) T = std::max<int64_t>(T, 1);
     } else {
       T = dsp.num_teams > 0 ? dsp.num_teams : 1;
     }
@@ -813,6 +834,11 @@ upir_status resolve_plan(upir_ctx *c, const upir_spmd *spmd_in, upir_loop_obj *l
     unsigned char pay[128];
     if (resolve_payload(c, lp, pay) == UPIR_OK && jacobi_tile_supports(*(const JacobiP *)pay, L, S))
       v = V_JACOBI_TILE;
+    c->err.clear();
+  } else if (lp->kind == UPIR_BODY_FILTER7 && S.tiled) {
+    unsigned char pay[128];
+    if (resolve_payload(c, lp, pay) == UPIR_OK && filter7_tile_supports(*(const Filter7P *)pay, L, S))
+      v = V_FILTER7_TILE;
     c->err.clear();
   } else if (is_matmul(lp->kind) && S.tiled) {
     unsigned char pay[sizeof(MatmulP) + 16];
@@ -934,6 +960,7 @@ upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for
   switch (pl.variant) {
     case V_STREAM4: e = launch_stream4(lp->kind, pay, pl.L, S, R, c->stream); break;
     case V_JACOBI_TILE: e = launch_jacobi_tile(*(const JacobiP *)pay, pl.L, S, R, c->stream); break;
+    case V_FILTER7_TILE: e = launch_filter7_tile(*(const Filter7P *)pay, pl.L, S, R, c->stream); break;
     case V_MATVEC_WAVE: e = launch_matvec_wave(*(const MatvecP *)pay, pl.L, S, R, c->stream); break;
     case V_MATMUL_MFMA: {
       const MatmulP &p = *(const MatmulP *)pay;

@@ -11,10 +11,11 @@ namespace upir {
 enum Variant : int32_t {
   V_GENERIC = 0,      // schedule-exact generic worksharing kernel
   V_STREAM4 = 1,      // 1-D, static chunk 4, vectorised (AXPY, SUM f32, COVER)
-  V_JACOBI_TILE = 2,  // tiled Jacobi with LDS halo
+  V_JACOBI_TILE = 2,  // tiled Jacobi, wavefront strips
   V_MATVEC_WAVE = 3,  // one wavefront per row
   V_MATMUL_MFMA = 4,  // MFMA tiles over C
   V_DYNAMIC = 5,      // dynamic / guided claim loop (generic bodies)
+  V_FILTER7_TILE = 6, // tiled 7 x 7 filter, wavefront strips
 };
 
 // Body payloads with device pointers already resolved.
@@ -29,6 +30,7 @@ struct MatmulP {
 struct MatvecP { const float *A; const float *x; float *y; int64_t cols, lda; };
 struct OwnerP { int32_t *out; };
 struct CoverP { int32_t *count; };
+struct Filter7P { const float *src; float *dst; const float *w; int64_t ld; };
 
 hipError_t launch_generic(int32_t body, const void *payload, const LoopK &L, const SchedK &S,
                           const RedK &R, hipStream_t st);
@@ -37,6 +39,8 @@ hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, con
 hipError_t launch_fold(const FoldK &F, hipStream_t st);
 hipError_t launch_jacobi_tile(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R,
                               hipStream_t st);
+hipError_t launch_filter7_tile(const Filter7P &p, const LoopK &L, const SchedK &S, const RedK &R,
+                               hipStream_t st);
 hipError_t launch_matvec_wave(const MatvecP &p, const LoopK &L, const SchedK &S, const RedK &R,
                               hipStream_t st);
 // MFMA matmul over tiles of C (tile[0] x tile[1]); S gives the team schedule over tiles.
@@ -47,5 +51,6 @@ hipError_t launch_bf16_split(const MatmulP &p, bool need_lo, hipStream_t st);
 
 // Jacobi tiled kernel constraints.
 bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S);
+bool filter7_tile_supports(const Filter7P &p, const LoopK &L, const SchedK &S);
 
 }  // namespace upir

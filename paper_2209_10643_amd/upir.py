@@ -27,12 +27,13 @@ UPIR_TARGET_GPU, UPIR_TARGET_CPU, UPIR_TARGET_CLUSTER = 1, 2, 3
 UPIR_DIST_TEAMS_UNITS, UPIR_DIST_TEAMS, UPIR_DIST_UNITS = 0, 1, 2
 UPIR_RED_NONE, UPIR_RED_SUM, UPIR_RED_MAX, UPIR_RED_MIN = 0, 1, 2, 3
 (UPIR_BODY_AXPY, UPIR_BODY_SUM, UPIR_BODY_JACOBI5, UPIR_BODY_MATMUL_F32, UPIR_BODY_MATMUL_BF16,
- UPIR_BODY_MATMUL_SPLIT3, UPIR_BODY_MATVEC, UPIR_BODY_OWNER, UPIR_BODY_COVER) = range(1, 10)
+ UPIR_BODY_MATMUL_SPLIT3, UPIR_BODY_MATVEC, UPIR_BODY_OWNER, UPIR_BODY_COVER, UPIR_BODY_FILTER7) = range(1, 11)
 UPIR_DT_F32, UPIR_DT_F64, UPIR_DT_I32, UPIR_DT_I64 = 1, 2, 3, 4
 UPIR_DEP_IN, UPIR_DEP_OUT, UPIR_DEP_INOUT = 1, 2, 3
 UPIR_TASKWAIT_PLAIN, UPIR_TASKWAIT_BATCHED = 0, 1
 UPIR_MLP_PARAMS = 6337
-VARIANTS = {0: "generic", 1: "stream4", 2: "jacobi_tile", 3: "matvec_wave", 4: "matmul_mfma", 5: "dynamic"}
+VARIANTS = {0: "generic", 1: "stream4", 2: "jacobi_tile", 3: "matvec_wave", 4: "matmul_mfma", 5: "dynamic",
+            6: "filter7_tile"}
 
 # ---------------------------------------------------------------- structures
 class upir_spmd(C.Structure):
@@ -86,6 +87,10 @@ class upir_owner_args(C.Structure):
 
 class upir_cover_args(C.Structure):
     _fields_ = [("count", C.c_void_p)]
+
+
+class upir_filter7_args(C.Structure):
+    _fields_ = [("src", C.c_void_p), ("dst", C.c_void_p), ("w", C.c_void_p), ("ld", C.c_int64)]
 
 
 class upir_body(C.Structure):

@@ -112,6 +112,12 @@ def test_loop_validation(hctx):
     mm = U.upir_matmul_args(0x1000, 0x2000, 0x3000, 8, 8, 16, 16, None, 0)
     assert _loop_status(h, [(1, 16, 1), (0, 16, 1)], U.UPIR_BODY_MATMUL_F32, mm) == U.UPIR_EUNSUPPORTED
     assert _loop_status(h, [(0, 16, 1), (0, 16, 1)], U.UPIR_BODY_MATMUL_F32, mm) == U.UPIR_OK
+    f7 = U.upir_filter7_args(0x1000, 0x2000, 0x3000, 64)
+    assert _loop_status(h, [(3, 61, 1), (3, 61, 1)], U.UPIR_BODY_FILTER7, f7) == U.UPIR_OK
+    assert _loop_status(h, [(3, 61, 1)], U.UPIR_BODY_FILTER7, f7) == U.UPIR_EINVAL            # 2-D only
+    assert _loop_status(h, [(3, 61, 1)] * 2, U.UPIR_BODY_FILTER7, f7, red=R) == U.UPIR_EINVAL  # no reduction
+    f7 = U.upir_filter7_args(0x1000, 0x2000, 0x3000, 0)
+    assert _loop_status(h, [(3, 61, 1)] * 2, U.UPIR_BODY_FILTER7, f7) == U.UPIR_EINVAL        # pitch
 
 
 def test_launch_needs_device(hctx):
