@@ -1,6 +1,6 @@
 """Benchmark of the UPIR data-parallel loop library on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--configs 1,1L,0,2,3,4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--configs 1,1L,0,2,3,4,P]
                     [--no-cpu-baseline]
 
 One step = one pass of the headline workload: a 4096 x 4096 float32 Jacobi
@@ -219,6 +219,117 @@ def bench_axpy(torch, ctx, timer, reps=1000):
     for h in (lp, lb, ls):
         ctx.free(h)
     del xb, yb
+    return out
+
+
+# ------------------------------------------------- the paper's size grids
+# The UPIR series of the paper's four offloading plots (sec. 6 figures: AXPY,
+# matmul, matvec, stencil with filter size 7), ms per run, mean of 10 runs, on
+# one V100 with its host; end-to-end offload times. Context only.
+PAPER_UPIR_MS = {
+    "axpy": {10240: 13.85, 102400: 14.61, 1024000: 21.54, 10240000: 74.75, 102400000: 702.39},
+    "matmul": {64: 13.91, 128: 17.49, 256: 27.6, 512: 135.03, 1024: 976.88},
+    "matvec": {1024: 17.88, 2048: 20.7, 4096: 44.2, 8192: 145.74, 16384: 583.45},
+    "stencil7": {64: 13.69, 128: 15.14, 256: 15.7, 512: 20.32, 1024: 28.72, 2048: 56.47},
+}
+
+
+def bench_paper_grid(torch, ctx, reps=10):
+    """The paper's four kernels over its size grids, from host (numpy) arrays:
+    map(to / tofrom / from), one offloaded loop, unmap, as one offload region;
+    `end_to_end_ms` is its mean over `reps` runs after one warm-up, as the
+    paper averages 10. `kernel_us` is the loop alone on device-resident data
+    (HIP events around `reps` back-to-back launches)."""
+    out = {}
+
+    def host(seed, stream, n):
+        return synth.uniform_pm1_torch(seed, stream, n, device="cuda").cpu().numpy()
+
+    def region(maps, make_loop):
+        for p, nb, mt in maps:
+            U.upir_data_map(ctx.h, p, nb, mt, U.UPIR_ACCESS_RO if mt == U.UPIR_MAP_TO else U.UPIR_ACCESS_RW, None)
+        lp = make_loop()
+        ctx.launch(lp)
+        for p, nb, mt in reversed(maps):
+            U.upir_data_unmap(ctx.h, p, mt)
+        ctx.free(lp)
+
+    def timed(maps, make_loop):
+        region(maps, make_loop)  # warm-up
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            region(maps, make_loop)
+            t.append((time.perf_counter() - t0) * 1e3)
+        # device-resident loop time
+        for p, nb, mt in maps:
+            U.upir_data_map(ctx.h, p, nb, mt, U.UPIR_ACCESS_RW, None)
+        lp = make_loop()
+        ctx.launch(lp)
+        ctx.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            ctx.launch(lp)
+        b.record()
+        b.synchronize()
+        k_us = a.elapsed_time(b) / reps * 1e3
+        for p, nb, mt in reversed(maps):
+            U.upir_data_unmap(ctx.h, p, U.UPIR_MAP_ALLOC)
+        ctx.free(lp)
+        return round(sum(t) / len(t), 3), round(k_us, 2)
+
+    rows = []
+    for N in PAPER_UPIR_MS["axpy"]:
+        x, y = host(70, 0, N), host(70, 1, N)
+        maps = [(x.ctypes.data, x.nbytes, U.UPIR_MAP_TO), (y.ctypes.data, y.nbytes, U.UPIR_MAP_TOFROM)]
+        mk = lambda: ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, x.ctypes.data, y.ctypes.data),
+                              [(0, N, 1)], None, None, device_ptrs=False)
+        e2e, k = timed(maps, mk)
+        rows.append({"N": N, "end_to_end_ms": e2e, "kernel_us": k, "GBps_kernel": round(12 * N / k / 1e3, 1),
+                     "paper_upir_ms": PAPER_UPIR_MS["axpy"][N]})
+    out["axpy"] = rows
+    rows = []
+    for N in PAPER_UPIR_MS["matvec"]:
+        A, x = host(71, 0, N * N), host(71, 1, N)
+        y = np.zeros(N, np.float32)
+        maps = [(A.ctypes.data, A.nbytes, U.UPIR_MAP_TO), (x.ctypes.data, x.nbytes, U.UPIR_MAP_TO),
+                (y.ctypes.data, y.nbytes, U.UPIR_MAP_FROM)]
+        mk = lambda: ctx.loop(U.UPIR_BODY_MATVEC, U.upir_matvec_args(A.ctypes.data, x.ctypes.data, y.ctypes.data, N, N),
+                              [(0, N, 1)], None, None, device_ptrs=False)
+        e2e, k = timed(maps, mk)
+        rows.append({"N": N, "end_to_end_ms": e2e, "kernel_us": k, "GBps_kernel": round((4 * N * N + 8 * N) / k / 1e3, 1),
+                     "paper_upir_ms": PAPER_UPIR_MS["matvec"][N]})
+        del A
+    out["matvec"] = rows
+    rows = []
+    for N in PAPER_UPIR_MS["matmul"]:
+        A, B = host(72, 0, N * N), host(72, 1, N * N)
+        Cm = np.zeros(N * N, np.float32)
+        maps = [(A.ctypes.data, A.nbytes, U.UPIR_MAP_TO), (B.ctypes.data, B.nbytes, U.UPIR_MAP_TO),
+                (Cm.ctypes.data, Cm.nbytes, U.UPIR_MAP_FROM)]
+        mk = lambda: ctx.loop(U.UPIR_BODY_MATMUL_F32, U.upir_matmul_args(A.ctypes.data, B.ctypes.data, Cm.ctypes.data,
+                                                                          N, N, N, N, None, 0),
+                              [(0, N, 1), (0, N, 1)], None, None, device_ptrs=False)
+        e2e, k = timed(maps, mk)
+        rows.append({"N": N, "end_to_end_ms": e2e, "kernel_us": k, "TFLOPs_kernel": round(2 * N ** 3 / k / 1e6, 2),
+                     "paper_upir_ms": PAPER_UPIR_MS["matmul"][N]})
+    out["matmul_f32"] = rows
+    rows = []
+    for N in PAPER_UPIR_MS["stencil7"]:
+        src, w = host(73, 0, N * N), host(73, 1, 49) * np.float32(0.25)
+        dst = np.zeros(N * N, np.float32)
+        maps = [(src.ctypes.data, src.nbytes, U.UPIR_MAP_TO), (w.ctypes.data, w.nbytes, U.UPIR_MAP_TO),
+                (dst.ctypes.data, dst.nbytes, U.UPIR_MAP_FROM)]
+        mk = lambda: ctx.loop(U.UPIR_BODY_FILTER7, U.upir_filter7_args(src.ctypes.data, dst.ctypes.data, w.ctypes.data, N),
+                              [(3, N - 3, 1), (3, N - 3, 1)], None, None, device_ptrs=False)
+        e2e, k = timed(maps, mk)
+        pts = (N - 6) ** 2
+        rows.append({"N": N, "end_to_end_ms": e2e, "kernel_us": k, "Gpts_kernel": round(pts / k / 1e3, 2),
+                     "TFLOPs_kernel": round(98 * pts / k / 1e6, 2), "paper_upir_ms": PAPER_UPIR_MS["stencil7"][N]})
+    out["stencil7"] = rows
+    out["note"] = ("end_to_end_ms: map + loop + unmap from pageable host arrays, mean of 10 after a warm-up "
+                   "(the paper's V100 series, paper_upir_ms, are end-to-end offload times and context only)")
     return out
 
 
@@ -531,9 +642,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--configs", default="1,1L,0,2,3,4",
+    ap.add_argument("--configs", default="1,1L,0,2,3,4,P",
                     help="1 Jacobi 4096^2 (always timed: the headline), 1L Jacobi 16384^2, 0 AXPY+sum, "
-                         "2 matmul, 3 batched tasks, 4 learned schedule")
+                         "2 matmul, 3 batched tasks, 4 learned schedule, P the paper's size grids")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (known bytes) to scale HBM counters")
@@ -597,6 +708,9 @@ def main():
     if "1L" in configs:
         log("jacobi 16384^2 (beyond the MALL)")
         extras["jacobi_16384"] = bench_jacobi_large(torch, ctx)
+    if "P" in configs:
+        log("the paper's size grids (AXPY, matvec, matmul, 7x7 stencil), host arrays")
+        extras["paper_grid"] = bench_paper_grid(torch, ctx)
     if "0" in configs:
         log("axpy")
         extras["axpy_sum"] = bench_axpy(torch, ctx, timer)

@@ -419,7 +419,7 @@ __device__ __forceinline__ void jacobi_load_row(const float *row, int64_t c0, in
 
 // Rows [ra, rb) of one wavefront's strip, columns of this lane. EDGE is the
 // path of tiles that cross the loop box's column bounds [jlo, jhi).
-template <bool EDGE, int RED>
+template <bool EDGE, int RED, bool NT>
 __device__ __forceinline__ void jacobi_strip(const JacobiP &p, int64_t ra, int64_t rb, int64_t c0, int lane, int64_t clo,
                                     int64_t chi, int64_t jlo, int64_t jhi, ResidualAcc<RED> &acc) {
   const int64_t ld = p.ld;
@@ -448,7 +448,8 @@ __device__ __forceinline__ void jacobi_strip(const JacobiP &p, int64_t ra, int64
       v.w = ((up.w + S.w) + (mid.z + Ep)) * 0.25f;
       float *out = p.dst + (r + q) * ld + c0;
       if (!EDGE || (c0 >= jlo && c0 + 3 < jhi)) {
-        __builtin_nontemporal_store(v, (f32x4 *)out);  // read back only by the next sweep
+        if (NT) __builtin_nontemporal_store(v, (f32x4 *)out);
+        else *(f32x4 *)out = v;
         if (RED) {
           acc.add(v.x, mid.x);
           acc.add(v.y, mid.y);
@@ -472,7 +473,10 @@ __device__ __forceinline__ void jacobi_strip(const JacobiP &p, int64_t ra, int64
   }
 }
 
-template <int TH, int RED>
+// NT: the grids exceed the last-level cache, so the new grid is stored with
+// the non-temporal hint (a grid that fits is read back from that cache by the
+// next sweep and is stored normally).
+template <int TH, int RED, bool NT>
 __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP p, RedK R) {
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, NW = blockDim.x / WAVE;
   const int team = xcd_team(blockIdx.x, gridDim.x);
@@ -489,11 +493,11 @@ __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP
     if (ra >= rb) return;
     const int64_t c0 = j0 + 4 * lane;
     if (j0 >= jlo && j0 + JT_W <= jhi) {
-      jacobi_strip<false, RED>(p, ra, rb, c0, lane, j0 - 1, j0 + JT_W, jlo, jhi, acc);
+      jacobi_strip<false, RED, NT>(p, ra, rb, c0, lane, j0 - 1, j0 + JT_W, jlo, jhi, acc);
     } else {
       // columns read by in-box points of this tile (inclusive)
       const int64_t clo = (j0 > jlo ? j0 : jlo) - 1, chi = (j0 + JT_W < jhi ? j0 + JT_W : jhi);
-      jacobi_strip<true, RED>(p, ra, rb, c0, lane, clo, chi, jlo, jhi, acc);
+      jacobi_strip<true, RED, NT>(p, ra, rb, c0, lane, clo, chi, jlo, jhi, acc);
     }
   };
 
@@ -523,16 +527,23 @@ bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
   return true;
 }
 
-template <int TH>
-static hipError_t go_jacobi(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
-  const size_t lds = 0;
+template <int TH, bool NT>
+static hipError_t go_jacobi_nt(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
+  const dim3 g(S.T), b(S.U);
   switch (R.op) {
-    case RED_NONE: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_NONE>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R); break;
-    case RED_SUM: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_SUM>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R); break;
-    case RED_MAX: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_MAX>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R); break;
-    default: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_MIN>), dim3(S.T), dim3(S.U), lds, st, L, S, p, R); break;
+    case RED_NONE: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_NONE, NT>), g, b, 0, st, L, S, p, R); break;
+    case RED_SUM: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_SUM, NT>), g, b, 0, st, L, S, p, R); break;
+    case RED_MAX: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_MAX, NT>), g, b, 0, st, L, S, p, R); break;
+    default: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_MIN, NT>), g, b, 0, st, L, S, p, R); break;
   }
   return hipGetLastError();
+}
+
+template <int TH>
+static hipError_t go_jacobi(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
+  // source and destination rows the sweep touches, against the 256 MB cache
+  const uint64_t bytes = 2ull * (uint64_t)(L.cnt[0] + 2) * (uint64_t)p.ld * 4u;
+  return bytes > (256ull << 20) ? go_jacobi_nt<TH, true>(p, L, S, R, st) : go_jacobi_nt<TH, false>(p, L, S, R, st);
 }
 
 hipError_t launch_jacobi_tile(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {

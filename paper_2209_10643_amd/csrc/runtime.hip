@@ -655,21 +655,21 @@ void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sc
       }
       break;
     case UPIR_BODY_JACOBI5:
-      // tiles of 64 rows (16-row strips per wavefront) once the grid fills
-      // the chip with them, 16 rows below that
+    case UPIR_BODY_FILTER7: {
+      // the tallest tile (longest wavefront strips) that still gives every
+      // SIMD four wavefronts: at least 4 x CUs tiles of 4 wavefronts each
       sc.policy = UPIR_SCHED_STATIC;
-      sc.tile[0] = lp->n >= (1LL << 22) ? 64 : 16;
       sc.tile[1] = 256;
+      sc.tile[0] = 4;
+      const int64_t ct = cdiv(std::max<int64_t>(lp->cnt[1], 1), 256);
+      for (int th : {64, 32, 16, 8})
+        if (cdiv(std::max<int64_t>(lp->cnt[0], 1), th) * ct >= 4LL * c->num_cus) {
+          sc.tile[0] = th;
+          break;
+        }
       sp.num_teams = 0;  // one tile per team
       break;
-    case UPIR_BODY_FILTER7:
-      // 7 x 7 filter: strips of 16 rows per wavefront on large grids (each
-      // input row feeds seven output rows), 4 rows on small ones
-      sc.policy = UPIR_SCHED_STATIC;
-      sc.tile[0] = lp->n >= (1LL << 20) ? 64 : 16;
-      sc.tile[1] = 256;
-      sp.num_teams = 0;
-      break;
+    }
     case UPIR_BODY_MATMUL_F32:
     case UPIR_BODY_MATMUL_BF16:
     case UPIR_BODY_MATMUL_SPLIT3: {
