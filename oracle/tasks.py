@@ -38,17 +38,22 @@ def _mix64(z: int) -> int:
     return z ^ (z >> 31)
 
 
-def depend_edges(deps):
+def depend_edges(deps, groups=None):
     """Predecessor sets from per-task depend lists.
 
     ``deps[j]`` is a list of (address, type) pairs for task j, in creation
     order. Returns ``preds[j]``, a sorted list of distinct task ids.
+    ``groups[j]`` (optional) names the taskloop that generated task j: tasks
+    of one taskloop carry the taskloop's depend list and are siblings that do
+    not wait for each other (None: a task of its own).
     """
     preds = []
     for j, dl in enumerate(deps):
         p = set()
         for addr, typ in dl:
             for i in range(j):
+                if groups is not None and groups[j] is not None and groups[i] == groups[j]:
+                    continue
                 for addr_i, typ_i in deps[i]:
                     if addr_i != addr:
                         continue
@@ -58,6 +63,35 @@ def depend_edges(deps):
                         p.add(i)
         preds.append(sorted(p))
     return preds
+
+
+def taskloop_count(n: int, grainsize: int = 0, num_tasks: int = 0, default: int = 1) -> int:
+    """Number of tasks a taskloop makes of ``n`` iterations (sec. 3.2 taskloop
+    fields, read as OpenMP's): ``num_tasks(k)`` asks for k tasks (at most one
+    per iteration); ``grainsize(g)`` for floor(n / g) tasks, so each has at
+    least g iterations (and fewer than 2g); with both, the smaller count;
+    with neither, ``default``. No iterations: no tasks."""
+    if n <= 0:
+        return 0
+    cands = []
+    if num_tasks > 0:
+        cands.append(min(num_tasks, n))
+    if grainsize > 0:
+        cands.append(max(1, n // grainsize))
+    g = min(cands) if cands else min(max(default, 1), n)
+    return max(1, g)
+
+
+def taskloop_blocks(n: int, grainsize: int = 0, num_tasks: int = 0, default: int = 1):
+    """The iteration ranges [lo, hi) of a taskloop's tasks, in task order:
+    near-equal contiguous blocks, the first n mod G one longer."""
+    g = taskloop_count(n, grainsize, num_tasks, default)
+    out = []
+    q, r = divmod(n, g) if g else (0, 0)
+    for t in range(g):
+        lo = t * q + min(t, r)
+        out.append((lo, lo + q + (1 if t < r else 0)))
+    return out
 
 
 def tokens(preds):

@@ -126,3 +126,42 @@ def test_adam_first_step_is_signed_lr():
         step = P[k] - P2[k]
         assert np.allclose(step, 1e-3 * g[k] / (np.abs(g[k]) + 1e-8), rtol=1e-12, atol=0)
         assert np.allclose(m[k], 0.1 * g[k]) and np.allclose(v[k], 0.001 * g[k] ** 2)
+
+
+# ------------------------------------------------------------- taskloop ----
+
+@pytest.mark.parametrize("n,g,k", [(100, 7, 0), (100, 0, 7), (100, 30, 5), (100, 0, 500), (5, 10, 0),
+                                   (1, 0, 3), (0, 3, 3), (1000003, 4096, 0)])
+def test_taskloop_blocks_cover_and_sizes(n, g, k):
+    blocks = tasks.taskloop_blocks(n, g, k, default=4)
+    if n == 0:
+        assert blocks == []
+        return
+    # contiguous, in order, covering [0, n) exactly once
+    assert blocks[0][0] == 0 and blocks[-1][1] == n
+    assert all(a[1] == b[0] for a, b in zip(blocks, blocks[1:]))
+    sizes = [hi - lo for lo, hi in blocks]
+    assert max(sizes) - min(sizes) <= 1 and min(sizes) >= 1
+    G = len(blocks)
+    if k and not g:
+        assert G == min(k, n)
+    if g and not k:
+        assert G == max(1, n // g)
+        if n >= g:                      # OpenMP: at least g and fewer than 2g per task
+            assert min(sizes) >= g and max(sizes) < 2 * g
+    if g and k:
+        assert G == min(k, n, max(1, n // g))
+
+
+def test_taskloop_siblings_do_not_wait_for_each_other():
+    X, Y = 0x100, 0x200
+    deps = [[(X, tasks.OUT)],                                   # 0: a task writing X
+            [(X, tasks.IN), (Y, tasks.OUT)], [(X, tasks.IN), (Y, tasks.OUT)], [(X, tasks.IN), (Y, tasks.OUT)],
+            [(Y, tasks.IN)]]                                    # 4: reads what the taskloop wrote
+    groups = [None, 7, 7, 7, None]
+    preds = tasks.depend_edges(deps, groups)
+    assert preds == [[], [0], [0], [0], [1, 2, 3]]
+    # without the grouping the three out-tasks would chain
+    assert tasks.depend_edges(deps) == [[], [0], [0, 1], [0, 1, 2], [1, 2, 3]]
+    # a one-task taskloop is an ordinary task
+    assert tasks.depend_edges(deps[:2], [None, 3]) == tasks.depend_edges(deps[:2])
