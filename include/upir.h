@@ -278,6 +278,21 @@ typedef struct { const void *addr; int32_t type; int32_t pad_; } upir_depend;
  * stay alive until taskwait. */
 upir_status upir_task(upir_ctx *ctx, const upir_spmd *spmd, upir_loop_h loop,
                       const upir_depend *deps, int32_t ndeps, int64_t *task_id);
+/* Taskloop (sec. 3.2, loop parallelization by tasking: fields grainsize and
+ * num_tasks). The 1-D `loop` (AXPY, MATVEC or COVER; no reduction) is cut
+ * into G tasks of near-equal contiguous iteration blocks, the first n mod G
+ * one longer: num_tasks > 0 asks for min(num_tasks, n) tasks, grainsize > 0
+ * for max(1, n / grainsize) (each task then has at least grainsize and fewer
+ * than 2 x grainsize iterations); with both the smaller count; with neither
+ * one task per 65536 iterations (at least one). No iterations: no tasks.
+ * `deps` apply to the taskloop as a whole: every generated task waits for
+ * what a single task with these deps would wait for, the generated tasks do
+ * not wait for each other, and later tasks that name an address wait for all
+ * of them. *first_task gets the first task id, *count the number G; ids are
+ * consecutive. Tasks run at the next taskwait, in either mode. */
+upir_status upir_taskloop(upir_ctx *ctx, const upir_spmd *spmd, upir_loop_h loop, int64_t grainsize,
+                          int64_t num_tasks, const upir_depend *deps, int32_t ndeps, int64_t *first_task,
+                          int64_t *count);
 /* Predecessors of task `id` as computed from the depend lists (sorted). */
 upir_status upir_task_preds(upir_ctx *ctx, int64_t id, int64_t *preds, int32_t cap, int32_t *count);
 #define UPIR_TASKWAIT_PLAIN   0  /* one kernel launch per task, in index order */

@@ -58,6 +58,7 @@ struct TaskRec {
   upir_spmd spmd;
   upir_loop_h loop;
   std::vector<int64_t> preds;
+  int64_t lo = 0, hi = -1;  // iteration block [lo, hi) of a taskloop task; hi < 0: the whole loop
 };
 
 struct AddrUse {

@@ -416,6 +416,10 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
     d.n = lp->n;
     d.lb = lp->loop.dim[0].lb;
     d.step = lp->loop.dim[0].step;
+    if (c->tasks[j].hi >= 0) {  // a taskloop task: its block of the loop's iterations
+      d.lb += c->tasks[j].lo * d.step;
+      d.n = c->tasks[j].hi - c->tasks[j].lo;
+    }
     int64_t tile = task_tile(c, lp);
     if (lp->kind != UPIR_BODY_MATVEC) tile = std::max<int64_t>(4, (tile + 3) / 4 * 4);
     d.tile = std::max<int64_t>(1, tile);
@@ -453,8 +457,10 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
       d.vec = (p.lda % 4 == 0) && ((uintptr_t)p.A % 16 == 0) && ((uintptr_t)p.x % 16 == 0);
     } else {
       const CoverP &p = *(const CoverP *)pay;
-      d.cnt = p.count;
-      d.vec = d.step == 1 && d.lb == 0;
+      // count[k] is indexed by the loop's iteration number: a taskloop task's
+      // local numbering starts at its block
+      d.cnt = p.count + (c->tasks[j].hi >= 0 ? c->tasks[j].lo : 0);
+      d.vec = d.step == 1 && lp->loop.dim[0].lb == 0 && (uintptr_t)d.cnt % 16 == 0;
     }
   }
   if (parts > (1LL << 31)) return upir_fail(c, UPIR_EINVAL, "too many reduction tiles");

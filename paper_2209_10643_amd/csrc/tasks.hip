@@ -23,25 +23,28 @@ static bool task_body_ok(int32_t k) {
   return k == UPIR_BODY_AXPY || k == UPIR_BODY_SUM || k == UPIR_BODY_MATVEC || k == UPIR_BODY_COVER;
 }
 
-extern "C" upir_status upir_task(upir_ctx *c, const upir_spmd *spmd, upir_loop_h lp, const upir_depend *deps,
-                                 int32_t ndeps, int64_t *task_id) {
-  if (!c) return UPIR_EINVAL;
+// Checks shared by upir_task and upir_taskloop; resolves the SPMD shape.
+static upir_status check_task(upir_ctx *c, const upir_spmd *spmd, upir_loop_h lp, const upir_depend *deps,
+                              int32_t ndeps, upir_spmd &sp) {
   if (!lp || !c->loops.count(lp)) return upir_fail(c, UPIR_EINVAL, "task: unknown loop handle");
   if (ndeps < 0 || (ndeps > 0 && !deps)) return upir_fail(c, UPIR_EDEPEND, "task: depend list");
   if (!task_body_ok(lp->kind))
     return upir_fail(c, UPIR_EUNSUPPORTED, "task: body %d is not offered as a task (AXPY, SUM, MATVEC, COVER)", lp->kind);
   if (lp->loop.collapse != 1) return upir_fail(c, UPIR_EUNSUPPORTED, "task: 1-D loops only");
-  if (lp->has_red && lp->red.result_on_host && lp->red.async)
-    return upir_fail(c, UPIR_EINVAL, "task: reductions of tasks complete at taskwait; async is meaningless");
   for (int32_t i = 0; i < ndeps; ++i)
     if (deps[i].type < UPIR_DEP_IN || deps[i].type > UPIR_DEP_INOUT)
       return upir_fail(c, UPIR_EDEPEND, "task: depend %d has type %d", i, deps[i].type);
   if (c->capturing) return upir_fail(c, UPIR_ESTATE, "task creation during graph capture");
-  upir_spmd sp{0, 0, UPIR_TARGET_GPU};
+  sp = upir_spmd{0, 0, UPIR_TARGET_GPU};
   if (spmd) sp = *spmd;
   if (sp.target == 0) sp.target = UPIR_TARGET_GPU;
   if (sp.target != UPIR_TARGET_GPU) return upir_fail(c, UPIR_EUNSUPPORTED, "task: only offload to the GPU");
-  const int64_t id = (int64_t)c->tasks.size();
+  return UPIR_OK;
+}
+
+// Predecessors of a new task (or of every task of a new taskloop) from the
+// depend list, before any of them is recorded.
+static std::vector<int64_t> preds_of(upir_ctx *c, const upir_depend *deps, int32_t ndeps) {
   std::vector<int64_t> preds;
   for (int32_t i = 0; i < ndeps; ++i) {
     auto it = c->addr.find((uintptr_t)deps[i].addr);
@@ -52,13 +55,63 @@ extern "C" upir_status upir_task(upir_ctx *c, const upir_spmd *spmd, upir_loop_h
   }
   std::sort(preds.begin(), preds.end());
   preds.erase(std::unique(preds.begin(), preds.end()), preds.end());
-  // record this task's uses (once per address and kind)
+  return preds;
+}
+
+static void record_uses(upir_ctx *c, const upir_depend *deps, int32_t ndeps, int64_t id) {
   for (int32_t i = 0; i < ndeps; ++i) {
     AddrUse &u = c->addr[(uintptr_t)deps[i].addr];
     if (u.all.empty() || u.all.back() != id) u.all.push_back(id);
     if (deps[i].type != UPIR_DEP_IN && (u.writers.empty() || u.writers.back() != id)) u.writers.push_back(id);
   }
-  c->tasks.push_back(TaskRec{sp, lp, std::move(preds)});
+}
+
+extern "C" upir_status upir_taskloop(upir_ctx *c, const upir_spmd *spmd, upir_loop_h lp, int64_t grainsize,
+                                     int64_t num_tasks, const upir_depend *deps, int32_t ndeps, int64_t *first_task,
+                                     int64_t *count) {
+  if (!c) return UPIR_EINVAL;
+  upir_spmd sp;
+  upir_status st = check_task(c, spmd, lp, deps, ndeps, sp);
+  if (st) return st;
+  if (grainsize < 0 || num_tasks < 0) return upir_fail(c, UPIR_EINVAL, "taskloop: negative grainsize / num_tasks");
+  if (lp->kind == UPIR_BODY_SUM || lp->has_red)
+    return upir_fail(c, UPIR_EUNSUPPORTED, "taskloop: loops with a reduction are not split into tasks");
+  const int64_t n = lp->n;
+  int64_t G = 0;
+  if (n > 0) {
+    G = INT64_MAX;
+    if (num_tasks > 0) G = std::min(G, std::min(num_tasks, n));
+    if (grainsize > 0) G = std::min(G, std::max<int64_t>(1, n / grainsize));
+    if (G == INT64_MAX) G = std::min<int64_t>(n, std::max<int64_t>(1, (n + 65535) / 65536));
+    G = std::max<int64_t>(1, G);
+  }
+  if (G > (1 << 20)) return upir_fail(c, UPIR_EINVAL, "taskloop: %lld tasks", (long long)G);
+  const int64_t first = (int64_t)c->tasks.size();
+  const std::vector<int64_t> preds = preds_of(c, deps, ndeps);
+  const int64_t q = G ? n / G : 0, r = G ? n % G : 0;
+  for (int64_t t = 0; t < G; ++t) {
+    TaskRec rec{sp, lp, preds};
+    rec.lo = t * q + std::min(t, r);
+    rec.hi = rec.lo + q + (t < r ? 1 : 0);
+    c->tasks.push_back(std::move(rec));
+  }
+  for (int64_t t = 0; t < G; ++t) record_uses(c, deps, ndeps, first + t);
+  if (first_task) *first_task = first;
+  if (count) *count = G;
+  return UPIR_OK;
+}
+
+extern "C" upir_status upir_task(upir_ctx *c, const upir_spmd *spmd, upir_loop_h lp, const upir_depend *deps,
+                                 int32_t ndeps, int64_t *task_id) {
+  if (!c) return UPIR_EINVAL;
+  upir_spmd sp;
+  upir_status st = check_task(c, spmd, lp, deps, ndeps, sp);
+  if (st) return st;
+  if (lp->has_red && lp->red.result_on_host && lp->red.async)
+    return upir_fail(c, UPIR_EINVAL, "task: reductions of tasks complete at taskwait; async is meaningless");
+  const int64_t id = (int64_t)c->tasks.size();
+  c->tasks.push_back(TaskRec{sp, lp, preds_of(c, deps, ndeps)});
+  record_uses(c, deps, ndeps, id);  // once per address and kind
   if (task_id) *task_id = id;
   return UPIR_OK;
 }
@@ -86,13 +139,37 @@ static void clear_tasks(upir_ctx *c) {
   c->addr.clear();
 }
 
+// The loop a task runs: the handle itself, or for a taskloop task a copy
+// whose 1-D range is the task's iteration block (same body and scratch).
+static upir_loop_obj task_view(const TaskRec &t) {
+  upir_loop_obj v = *t.loop;
+  if (t.hi >= 0) {
+    const int64_t lb = v.loop.dim[0].lb, step = v.loop.dim[0].step;
+    v.loop.dim[0].lb = lb + t.lo * step;
+    v.loop.dim[0].ub = lb + t.hi * step;
+    v.cnt[0] = t.hi - t.lo;
+    v.n = t.hi - t.lo;
+    if (v.kind == UPIR_BODY_COVER) {  // count[k] is indexed by iteration number
+      upir_cover_args a;
+      memcpy(&a, v.args, sizeof a);
+      a.count += t.lo;
+      memcpy(v.args, &a, sizeof a);
+    }
+  }
+  return v;
+}
+
 static upir_status run_plain(upir_ctx *c) {
   for (size_t j = 0; j < c->tasks.size(); ++j) {
     TaskRec &t = c->tasks[j];
+    // a taskloop task (no reduction, so nothing in the copy's scratch is
+    // resized) runs as a view; a whole-loop task runs its own handle
+    upir_loop_obj view = task_view(t);
+    upir_loop_obj *lp = t.hi >= 0 ? &view : t.loop;
     Plan pl;
-    upir_status st = resolve_plan(c, &t.spmd, t.loop, pl);
+    upir_status st = resolve_plan(c, &t.spmd, lp, pl);
     if (st) return st;
-    st = launch_plan(c, t.loop, pl, true);
+    st = launch_plan(c, lp, pl, true);
     if (st) return st;
     if (c->trace.tokens || c->trace.start_stamp || c->trace.done_stamp) {
       st = upir_plain_trace(c, (int64_t)j);

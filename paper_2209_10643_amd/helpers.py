@@ -116,6 +116,16 @@ class Context:
         U.upir_task(self.h, C.byref(spmd) if spmd is not None else None, loop, arr, len(deps), C.byref(tid))
         return tid.value
 
+    def taskloop(self, loop, grainsize=0, num_tasks=0, deps=(), spmd=None):
+        """Returns (first task id, number of tasks)."""
+        arr = (U.upir_depend * max(1, len(deps)))()
+        for i, (addr, typ) in enumerate(deps):
+            arr[i].addr, arr[i].type = addr, typ
+        first, cnt = C.c_int64(), C.c_int64()
+        U.upir_taskloop(self.h, C.byref(spmd) if spmd is not None else None, loop, grainsize, num_tasks, arr,
+                        len(deps), C.byref(first), C.byref(cnt))
+        return first.value, cnt.value
+
     def task_preds(self, tid):
         cnt = C.c_int32()
         U.upir_task_preds(self.h, tid, None, 0, C.byref(cnt))

@@ -140,6 +140,8 @@ _SIGS = {
     "upir_graph_launch": (None, [_ctx_p, C.c_void_p]),
     "upir_graph_destroy": (None, [_ctx_p, C.c_void_p]),
     "upir_task": (None, [_ctx_p, P(upir_spmd), C.c_void_p, P(upir_depend), C.c_int32, P(C.c_int64)]),
+    "upir_taskloop": (None, [_ctx_p, P(upir_spmd), C.c_void_p, C.c_int64, C.c_int64, P(upir_depend), C.c_int32,
+                             P(C.c_int64), P(C.c_int64)]),
     "upir_task_preds": (None, [_ctx_p, C.c_int64, P(C.c_int64), C.c_int32, P(C.c_int32)]),
     "upir_set_task_trace": (None, [_ctx_p, P(upir_task_trace)]),
     "upir_taskwait": (None, [_ctx_p, C.c_int32]),

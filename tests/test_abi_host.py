@@ -233,6 +233,69 @@ def test_depend_graph_matches_oracle(hctx, seed):
     assert _status("upir_taskwait", h, U.UPIR_TASKWAIT_PLAIN) == U.UPIR_ESTATE
 
 
+def _cover_loop(h, n, lb=0):
+    args = U.upir_cover_args(0x1000)
+    body = U.upir_body(U.UPIR_BODY_COVER, 1, C.cast(C.pointer(args), C.c_void_p), C.sizeof(args))
+    L = H.make_loop([(lb, lb + n, 1)])
+    lp = C.c_void_p()
+    U.upir_loop_parallel(h, C.byref(L), None, C.byref(body), None, C.byref(lp))
+    return lp
+
+
+def _add_taskloop(h, lp, deps, g=0, k=0):
+    arr = (U.upir_depend * max(1, len(deps)))()
+    for i, (addr, typ) in enumerate(deps):
+        arr[i].addr, arr[i].type = addr, typ
+    first, cnt = C.c_int64(), C.c_int64()
+    U.upir_taskloop(h, None, lp, g, k, arr, len(deps), C.byref(first), C.byref(cnt))
+    return first.value, cnt.value
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_taskloop_graph_matches_oracle(hctx, seed):
+    """Random mixes of tasks and taskloops: task counts from grainsize /
+    num_tasks and every predecessor list, against the oracle's rules."""
+    h = hctx
+    rng = np.random.default_rng(seed)
+    loops = {n: _cover_loop(h, n) for n in (1, 7, 100, 1000, 65537)}
+    deps, groups, ntasks = [], [], 0
+    for step in range(40):
+        dl = [(int(rng.integers(1, 7)) * 64, int(rng.integers(1, 4))) for _ in range(int(rng.integers(0, 3)))]
+        odl = [(a, TYPES[t]) for a, t in dl]
+        if rng.random() < 0.5:
+            n = int(rng.choice(list(loops)))
+            g, k = [(7, 0), (0, 5), (30, 4), (0, 0), (1000, 0)][int(rng.integers(0, 5))]
+            first, cnt = _add_taskloop(h, loops[n], dl, g, k)
+            assert first == ntasks
+            assert cnt == otasks.taskloop_count(n, g, k, default=max(1, -(-n // 65536)))
+            deps += [odl] * cnt
+            groups += [step] * cnt
+            ntasks += cnt
+        else:
+            assert _add_task(h, loops[7], dl) == ntasks
+            deps.append(odl)
+            groups.append(None)
+            ntasks += 1
+    want = otasks.depend_edges(deps, groups)
+    assert [_preds(h, j) for j in range(ntasks)] == want
+
+
+def test_taskloop_validation(hctx):
+    h = hctx
+    lp = _cover_loop(h, 100)
+    first, cnt = C.c_int64(), C.c_int64()
+    assert _status("upir_taskloop", h, None, lp, -1, 0, None, 0, C.byref(first), C.byref(cnt)) == U.UPIR_EINVAL
+    sa = U.upir_sum_args(0x1000, U.UPIR_DT_F32, 0)
+    body = U.upir_body(U.UPIR_BODY_SUM, 1, C.cast(C.pointer(sa), C.c_void_p), C.sizeof(sa))
+    L = H.make_loop([(0, 100, 1)])
+    R = H.make_red(U.UPIR_RED_SUM, 0x3000)
+    sl = C.c_void_p()
+    U.upir_loop_parallel(h, C.byref(L), None, C.byref(body), C.byref(R), C.byref(sl))
+    assert _status("upir_taskloop", h, None, sl, 10, 0, None, 0, C.byref(first), C.byref(cnt)) == U.UPIR_EUNSUPPORTED
+    empty = _cover_loop(h, 0)
+    assert _add_taskloop(h, empty, [], 4, 0) == (0, 0)   # no iterations, no tasks
+
+
 def test_task_validation(hctx):
     h = hctx
     lp = _task_loop(h)

@@ -206,3 +206,76 @@ def test_task_coverage(ctx, mode):
 def test_empty_taskwait(ctx):
     ctx.taskwait(U.UPIR_TASKWAIT_BATCHED)
     ctx.taskwait(U.UPIR_TASKWAIT_PLAIN)
+
+
+# ------------------------------------------------------------- taskloop ----
+
+MODES = [U.UPIR_TASKWAIT_PLAIN, U.UPIR_TASKWAIT_BATCHED]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_taskloop_axpy_and_matvec(ctx, mode):
+    """An AXPY cut by grainsize and a MATVEC cut by num_tasks: outputs equal
+    the oracle's (AXPY bit-exact, MATVEC normwise 1e-5)."""
+    note(f"taskloop axpy/matvec mode={mode}")
+    n = 1_000_003
+    x, y0 = synth.uniform_pm1(50, 0, n), synth.uniform_pm1(50, 1, n)
+    tx, ty = dev(x), dev(y0)
+    ax = ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, tx.data_ptr(), ty.data_ptr()), [(0, n, 1)])
+    first, cnt = ctx.taskloop(ax, grainsize=65536)
+    assert (first, cnt) == (0, otasks.taskloop_count(n, 65536))
+    rows = 3001
+    A, v = synth.uniform_pm1(51, 0, rows * 256).reshape(rows, 256), synth.uniform_pm1(51, 1, 256)
+    tA, tv, tyv = dev(A), dev(v), torch.zeros(rows, device="cuda")
+    mv = ctx.loop(U.UPIR_BODY_MATVEC, U.upir_matvec_args(tA.data_ptr(), tv.data_ptr(), tyv.data_ptr(), 256, 256),
+                  [(0, rows, 1)])
+    first2, cnt2 = ctx.taskloop(mv, num_tasks=7)
+    assert (first2, cnt2) == (cnt, 7)
+    ctx.taskwait(mode)
+    assert np.array_equal(ty.cpu().numpy(), bodies.axpy(2.5, x, y0))
+    assert bodies.frob_rel(tyv.cpu().numpy().astype(np.float64), bodies.matvec(A, v)) <= 1e-5
+    ctx.free(ax)
+    ctx.free(mv)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n,lb,g,k", [(300007, 0, 0, 37), (100000, 5, 4096, 0), (10, 0, 0, 64)])
+def test_taskloop_covers_each_iteration_once(ctx, mode, n, lb, g, k):
+    cnt = torch.zeros(n, dtype=torch.int32, device="cuda")
+    lp = ctx.loop(U.UPIR_BODY_COVER, U.upir_cover_args(cnt.data_ptr()), [(lb, lb + n, 1)])
+    _, G = ctx.taskloop(lp, grainsize=g, num_tasks=k)
+    assert G == otasks.taskloop_count(n, g, k)
+    ctx.taskwait(mode)
+    c = cnt.cpu().numpy()
+    assert (c == 1).all(), int((c != 1).sum())
+    ctx.free(lp)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_taskloop_in_a_task_graph(ctx, mode):
+    """task(out X) -> taskloop(in X, out Y) -> task(in Y): the taskloop's
+    tasks run after the first task, side by side, and before the last; the
+    token chain over the predecessors matches the oracle's graph."""
+    note(f"taskloop graph mode={mode}")
+    X, Y = 0x7000, 0x8000
+    bufs = [(synth.uniform_pm1(52, 2 * i, 50000), synth.uniform_pm1(52, 2 * i + 1, 50000)) for i in range(3)]
+    dbufs = [(dev(a), dev(b)) for a, b in bufs]
+    lps = [ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, tx.data_ptr(), ty.data_ptr()), [(0, 50000, 1)])
+           for tx, ty in dbufs]
+    ctx.task(lps[0], [(X, U.UPIR_DEP_OUT)])
+    first, G = ctx.taskloop(lps[1], num_tasks=5, deps=[(X, U.UPIR_DEP_IN), (Y, U.UPIR_DEP_OUT)])
+    last = ctx.task(lps[2], [(Y, U.UPIR_DEP_IN)])
+    assert (first, G, last) == (1, 5, 6)
+    deps = [[(X, otasks.OUT)]] + [[(X, otasks.IN), (Y, otasks.OUT)]] * 5 + [[(Y, otasks.IN)]]
+    want_preds = otasks.depend_edges(deps, [None] + [1] * 5 + [None])
+    assert [ctx.task_preds(j) for j in range(7)] == want_preds
+    tok = torch.zeros(7, dtype=torch.int64, device="cuda")
+    ctx.set_trace(tok.data_ptr())
+    ctx.taskwait(mode)
+    ctx.set_trace()
+    got = [int(v) & (2 ** 64 - 1) for v in tok.cpu().numpy().tolist()]
+    assert got == otasks.tokens(want_preds)
+    for (a, b), (_, ty) in zip(bufs, dbufs):
+        assert np.array_equal(ty.cpu().numpy(), bodies.axpy(2.5, a, b))
+    for lp in lps:
+        ctx.free(lp)
