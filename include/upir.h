@@ -293,6 +293,17 @@ upir_status upir_task(upir_ctx *ctx, const upir_spmd *spmd, upir_loop_h loop,
 upir_status upir_taskloop(upir_ctx *ctx, const upir_spmd *spmd, upir_loop_h loop, int64_t grainsize,
                           int64_t num_tasks, const upir_depend *deps, int32_t ndeps, int64_t *first_task,
                           int64_t *count);
+/* data_update as a task (sec. 4 explicit data movement with its depend
+ * field): copy `bytes` of the mapped range starting at `host` to the device
+ * (UPIR_TO_DEVICE) or back (UPIR_FROM_DEVICE), ordered only by `deps` with
+ * the rules of upir_task. It runs at the next upir_taskwait(PLAIN) on the
+ * context's copy queue, so it overlaps loop tasks it is not ordered with
+ * (host memory should be pinned for the copy engine to run asynchronously).
+ * bytes = 0: to the end of the mapping. The range must be mapped when the
+ * task runs (UPIR_ENOTMAPPED otherwise). Graphs and the BATCHED executor
+ * take no copy tasks (UPIR_EUNSUPPORTED at taskwait). */
+upir_status upir_task_update(upir_ctx *ctx, void *host, size_t bytes, int32_t dir, const upir_depend *deps,
+                             int32_t ndeps, int64_t *task_id);
 /* Predecessors of task `id` as computed from the depend lists (sorted). */
 upir_status upir_task_preds(upir_ctx *ctx, int64_t id, int64_t *preds, int32_t cap, int32_t *count);
 #define UPIR_TASKWAIT_PLAIN   0  /* one kernel launch per task, in index order */

@@ -153,6 +153,8 @@ extern "C" upir_status upir_finalize(upir_ctx *c) {
   for (void *p : c->retired) upir_dfree(c, p);
   upir_model_free(c);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  for (hipStream_t cs : c->copy_stream)
+    if (cs) (void)hipStreamDestroy(cs);
   delete c;
   return UPIR_OK;
 }
@@ -242,6 +244,17 @@ extern "C" upir_status upir_data_unmap(upir_ctx *c, void *host, int32_t map) {
   }
   upir_dfree(c, m.dev);
   c->table.erase(it);
+  return UPIR_OK;
+}
+
+upir_status upir_map_range(upir_ctx *c, const void *host, size_t *bytes, void **dev) {
+  const uintptr_t h = (uintptr_t)host;
+  Mapping *m = find_containing(c, h);
+  if (!m) return upir_fail(c, UPIR_ENOTMAPPED, "%p not mapped", host);
+  const size_t off = h - m->host;
+  if (*bytes == 0) *bytes = m->bytes - off;
+  if (off + *bytes > m->bytes) return upir_fail(c, UPIR_EINVAL, "range leaves its mapping");
+  *dev = (char *)m->dev + off;
   return UPIR_OK;
 }
 

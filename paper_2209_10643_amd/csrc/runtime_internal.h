@@ -59,6 +59,10 @@ struct TaskRec {
   upir_loop_h loop;
   std::vector<int64_t> preds;
   int64_t lo = 0, hi = -1;  // iteration block [lo, hi) of a taskloop task; hi < 0: the whole loop
+  // data_update task (loop == nullptr): host range and direction
+  void *host = nullptr;
+  size_t bytes = 0;
+  int32_t dir = 0;
 };
 
 struct AddrUse {
@@ -97,6 +101,7 @@ struct upir_ctx {
   bool none = false;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t copy_stream[2] = {nullptr, nullptr};  // data_update tasks to / from the device (on first use)
   upir_alloc_fn alloc = nullptr;
   upir_free_fn free_fn = nullptr;
   void *user = nullptr;
@@ -130,6 +135,9 @@ upir_status upir_hipfail(upir_ctx *c, hipError_t e, const char *what);
 void *upir_dalloc(upir_ctx *c, size_t bytes);
 void upir_dfree(upir_ctx *c, void *p);
 void upir_model_free(upir_ctx *c);
+// Device address of [host, host + bytes) inside one mapping (bytes = 0: to
+// the mapping's end, returned in *bytes).
+upir_status upir_map_range(upir_ctx *c, const void *host, size_t *bytes, void **dev);
 
 namespace upir {
 struct Plan {

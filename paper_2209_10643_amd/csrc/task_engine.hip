@@ -336,11 +336,18 @@ static upir_status plain_trace_buf(upir_ctx *c, unsigned long long **clock) {
   return UPIR_OK;
 }
 
-upir_status upir_plain_trace(upir_ctx *c, int64_t task) {
+upir_status upir_plain_trace_start(upir_ctx *c) {
   unsigned long long *clock = nullptr;
   upir_status st = plain_trace_buf(c, &clock);
   if (st) return st;
-  if (task == 0) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, c->stream, clock);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, c->stream, clock);
+  return UPIR_OK;
+}
+
+upir_status upir_plain_trace(upir_ctx *c, int64_t task, hipStream_t s) {
+  unsigned long long *clock = nullptr;
+  upir_status st = plain_trace_buf(c, &clock);
+  if (st) return st;
   const auto &preds = c->tasks[task].preds;
   // predecessor ids travel in a small device array owned by the task list
   int32_t *dp = nullptr;
@@ -348,18 +355,18 @@ upir_status upir_plain_trace(upir_ctx *c, int64_t task) {
     dp = (int32_t *)upir_dalloc(c, preds.size() * 4);
     if (!dp) return upir_fail(c, UPIR_ENOMEM, "trace preds");
     std::vector<int32_t> hp(preds.begin(), preds.end());
-    hipError_t e = hipMemcpyAsync(dp, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    hipError_t e = hipMemcpyAsync(dp, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       upir_dfree(c, dp);
       return upir_hipfail(c, e, "trace preds copy");
     }
   }
-  hipLaunchKernelGGL(k_plain_trace, dim3(1), dim3(64), 0, c->stream, (int32_t)task, dp, (int32_t)preds.size(),
+  hipLaunchKernelGGL(k_plain_trace, dim3(1), dim3(64), 0, s, (int32_t)task, dp, (int32_t)preds.size(),
                      c->trace.tokens, c->trace.start_stamp, c->trace.done_stamp, clock);
   hipError_t e = hipGetLastError();
   if (dp) {
-    hipError_t e2 = hipStreamSynchronize(c->stream);
+    hipError_t e2 = hipStreamSynchronize(s);
     upir_dfree(c, dp);
     if (e == hipSuccess) e = e2;
   }

@@ -17,7 +17,8 @@
 using namespace upir;
 
 upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **gout);  // task_engine.hip
-upir_status upir_plain_trace(upir_ctx *c, int64_t task);                              // task_engine.hip
+upir_status upir_plain_trace(upir_ctx *c, int64_t task, hipStream_t s);               // task_engine.hip
+upir_status upir_plain_trace_start(upir_ctx *c);                                      // task_engine.hip
 
 static bool task_body_ok(int32_t k) {
   return k == UPIR_BODY_AXPY || k == UPIR_BODY_SUM || k == UPIR_BODY_MATVEC || k == UPIR_BODY_COVER;
@@ -116,6 +117,33 @@ extern "C" upir_status upir_task(upir_ctx *c, const upir_spmd *spmd, upir_loop_h
   return UPIR_OK;
 }
 
+extern "C" upir_status upir_task_update(upir_ctx *c, void *host, size_t bytes, int32_t dir, const upir_depend *deps,
+                                        int32_t ndeps, int64_t *task_id) {
+  if (!c) return UPIR_EINVAL;
+  if (!host) return upir_fail(c, UPIR_EINVAL, "task_update: null host address");
+  if (dir != UPIR_TO_DEVICE && dir != UPIR_FROM_DEVICE) return upir_fail(c, UPIR_EINVAL, "task_update: direction");
+  if (ndeps < 0 || (ndeps > 0 && !deps)) return upir_fail(c, UPIR_EDEPEND, "task_update: depend list");
+  for (int32_t i = 0; i < ndeps; ++i)
+    if (deps[i].type < UPIR_DEP_IN || deps[i].type > UPIR_DEP_INOUT)
+      return upir_fail(c, UPIR_EDEPEND, "task_update: depend %d has type %d", i, deps[i].type);
+  if (c->capturing) return upir_fail(c, UPIR_ESTATE, "task creation during graph capture");
+  const int64_t id = (int64_t)c->tasks.size();
+  TaskRec rec{upir_spmd{0, 0, UPIR_TARGET_GPU}, nullptr, preds_of(c, deps, ndeps)};
+  rec.host = host;
+  rec.bytes = bytes;
+  rec.dir = dir;
+  c->tasks.push_back(std::move(rec));
+  record_uses(c, deps, ndeps, id);
+  if (task_id) *task_id = id;
+  return UPIR_OK;
+}
+
+static bool has_copy_tasks(const upir_ctx *c) {
+  for (const auto &t : c->tasks)
+    if (!t.loop) return true;
+  return false;
+}
+
 extern "C" upir_status upir_task_preds(upir_ctx *c, int64_t id, int64_t *preds, int32_t cap, int32_t *count) {
   if (!c || !count) return UPIR_EINVAL;
   if (id < 0 || id >= (int64_t)c->tasks.size()) return upir_fail(c, UPIR_EINVAL, "task id %lld", (long long)id);
@@ -159,22 +187,97 @@ static upir_loop_obj task_view(const TaskRec &t) {
   return v;
 }
 
+// Loop tasks run on the context stream in creation order; data_update tasks
+// run on two copy streams, one per direction (the link carries both
+// directions at once). An edge between tasks on different streams becomes
+// an event wait; an edge on one stream is kept by stream order. Creation
+// order is a topological order, so every event waited for has been recorded.
+static int task_queue(const TaskRec &t) { return !t.loop ? (t.dir == UPIR_TO_DEVICE ? 1 : 2) : 0; }
+
 static upir_status run_plain(upir_ctx *c) {
-  for (size_t j = 0; j < c->tasks.size(); ++j) {
-    TaskRec &t = c->tasks[j];
-    // a taskloop task (no reduction, so nothing in the copy's scratch is
-    // resized) runs as a view; a whole-loop task runs its own handle
-    upir_loop_obj view = task_view(t);
-    upir_loop_obj *lp = t.hi >= 0 ? &view : t.loop;
-    Plan pl;
-    upir_status st = resolve_plan(c, &t.spmd, lp, pl);
-    if (st) return st;
-    st = launch_plan(c, lp, pl, true);
-    if (st) return st;
-    if (c->trace.tokens || c->trace.start_stamp || c->trace.done_stamp) {
-      st = upir_plain_trace(c, (int64_t)j);
-      if (st) return st;
+  const size_t n = c->tasks.size();
+  const bool copies = has_copy_tasks(c);
+  const bool tracing = c->trace.tokens || c->trace.start_stamp || c->trace.done_stamp;
+  std::vector<hipEvent_t> ev;
+  auto cleanup = [&]() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  };
+  if (copies) {
+    if (c->capturing) return upir_fail(c, UPIR_EUNSUPPORTED, "data_update tasks are not captured in graphs");
+    for (int q = 0; q < 2; ++q)
+      if (!c->copy_stream[q] && hipStreamCreateWithFlags(&c->copy_stream[q], hipStreamNonBlocking) != hipSuccess)
+        return upir_fail(c, UPIR_EHIP, "copy stream");
+    ev.resize(n + 1, nullptr);
+    for (auto &e : ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        cleanup();
+        return upir_fail(c, UPIR_EHIP, "task events");
+      }
+  }
+  if (tracing) {
+    upir_status st = upir_plain_trace_start(c);
+    if (st) {
+      cleanup();
+      return st;
     }
+  }
+  hipStream_t qs[3] = {c->stream, c->copy_stream[0], c->copy_stream[1]};
+  if (copies) {  // the copy streams start after the work already on the context stream
+    hipError_t e = hipEventRecord(ev[n], c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(qs[1], ev[n], 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(qs[2], ev[n], 0);
+    if (e != hipSuccess) {
+      cleanup();
+      return upir_hipfail(c, e, "copy stream start");
+    }
+  }
+  for (size_t j = 0; j < n; ++j) {
+    TaskRec &t = c->tasks[j];
+    const bool is_copy = !t.loop;
+    const int q = task_queue(t);
+    hipStream_t s = qs[q];
+    upir_status st = UPIR_OK;
+    if (copies)
+      for (int64_t p : t.preds)
+        if (task_queue(c->tasks[p]) != q && hipStreamWaitEvent(s, ev[p], 0) != hipSuccess)
+          st = upir_fail(c, UPIR_EHIP, "task %zu: event wait", j);
+    if (!st && is_copy) {
+      size_t bytes = t.bytes;
+      void *dev = nullptr;
+      st = upir_map_range(c, t.host, &bytes, &dev);
+      if (!st) {
+        hipError_t e = t.dir == UPIR_TO_DEVICE ? hipMemcpyAsync(dev, t.host, bytes, hipMemcpyHostToDevice, s)
+                                               : hipMemcpyAsync(t.host, dev, bytes, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) st = upir_hipfail(c, e, "data_update task");
+      }
+    } else if (!st) {
+      // a taskloop task (no reduction, so nothing in the copy's scratch is
+      // resized) runs as a view; a whole-loop task runs its own handle
+      upir_loop_obj view = task_view(t);
+      upir_loop_obj *lp = t.hi >= 0 ? &view : t.loop;
+      Plan pl;
+      st = resolve_plan(c, &t.spmd, lp, pl);
+      if (!st) st = launch_plan(c, lp, pl, true);
+    }
+    if (!st && tracing) st = upir_plain_trace(c, (int64_t)j, s);
+    if (!st && copies && hipEventRecord(ev[j], s) != hipSuccess) st = upir_fail(c, UPIR_EHIP, "task event");
+    if (st) {
+      if (copies) {
+        (void)hipStreamSynchronize(qs[1]);
+        (void)hipStreamSynchronize(qs[2]);
+      }
+      cleanup();
+      return st;
+    }
+  }
+  if (copies) {  // let all three streams drain before the events go
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < 3; ++q) {
+      const hipError_t eq = hipStreamSynchronize(qs[q]);
+      if (e == hipSuccess) e = eq;
+    }
+    cleanup();
+    if (e != hipSuccess) return upir_hipfail(c, e, "copy streams");
   }
   return UPIR_OK;
 }
@@ -183,7 +286,7 @@ static upir_status deliver_task_results(upir_ctx *c) {
   bool any = false;
   for (auto &t : c->tasks) {
     upir_loop_obj *lp = t.loop;
-    if (lp->has_red && lp->red.result_on_host) {
+    if (lp && lp->has_red && lp->red.result_on_host) {
       hipError_t e = hipMemcpyAsync(lp->red.result, lp->scratch + SCR_RESULT, 8, hipMemcpyDeviceToHost, c->stream);
       if (e != hipSuccess) return upir_hipfail(c, e, "taskwait: result copy");
       any = true;
@@ -203,8 +306,10 @@ extern "C" upir_status upir_taskwait(upir_ctx *c, int32_t mode) {
   // results that live on the host are copied from each loop's result slot
   for (auto &t : c->tasks)
     for (auto &u : c->tasks)
-      if (&t != &u && t.loop == u.loop && t.loop->has_red && t.loop->red.result_on_host)
+      if (&t != &u && t.loop && t.loop == u.loop && t.loop->has_red && t.loop->red.result_on_host)
         return upir_fail(c, UPIR_EINVAL, "a loop with a host-result reduction can back only one task per taskwait");
+  if (mode == UPIR_TASKWAIT_BATCHED && has_copy_tasks(c))
+    return upir_fail(c, UPIR_EUNSUPPORTED, "data_update tasks run with taskwait PLAIN");
   upir_status st = settle(c);  // a deferred fold of an earlier loop runs before the tasks
   if (st) return st;
   st = mode == UPIR_TASKWAIT_PLAIN ? run_plain(c) : upir_batched_run(c, false, nullptr);
@@ -218,6 +323,7 @@ extern "C" upir_status upir_taskwait_graph(upir_ctx *c, int32_t mode, upir_graph
   if (mode != UPIR_TASKWAIT_PLAIN && mode != UPIR_TASKWAIT_BATCHED) return upir_fail(c, UPIR_EINVAL, "taskwait mode");
   if (c->none) return upir_fail(c, UPIR_ESTATE, "host-only context cannot run tasks");
   if (c->capturing) return upir_fail(c, UPIR_ESTATE, "already capturing");
+  if (has_copy_tasks(c)) return upir_fail(c, UPIR_EUNSUPPORTED, "data_update tasks are not captured in graphs");
   for (auto &t : c->tasks)
     if (t.loop->has_red && t.loop->red.result_on_host)
       return upir_fail(c, UPIR_EINVAL, "graph-built tasks need device results");

@@ -126,6 +126,15 @@ class Context:
                         len(deps), C.byref(first), C.byref(cnt))
         return first.value, cnt.value
 
+    def task_update(self, host, nbytes, direction, deps=()):
+        """data_update as a task (runs on the copy queue at taskwait PLAIN)."""
+        arr = (U.upir_depend * max(1, len(deps)))()
+        for i, (addr, typ) in enumerate(deps):
+            arr[i].addr, arr[i].type = addr, typ
+        tid = C.c_int64()
+        U.upir_task_update(self.h, host, nbytes, direction, arr, len(deps), C.byref(tid))
+        return tid.value
+
     def task_preds(self, tid):
         cnt = C.c_int32()
         U.upir_task_preds(self.h, tid, None, 0, C.byref(cnt))

@@ -142,6 +142,8 @@ _SIGS = {
     "upir_task": (None, [_ctx_p, P(upir_spmd), C.c_void_p, P(upir_depend), C.c_int32, P(C.c_int64)]),
     "upir_taskloop": (None, [_ctx_p, P(upir_spmd), C.c_void_p, C.c_int64, C.c_int64, P(upir_depend), C.c_int32,
                              P(C.c_int64), P(C.c_int64)]),
+    "upir_task_update": (None, [_ctx_p, C.c_void_p, C.c_size_t, C.c_int32, P(upir_depend), C.c_int32,
+                                P(C.c_int64)]),
     "upir_task_preds": (None, [_ctx_p, C.c_int64, P(C.c_int64), C.c_int32, P(C.c_int32)]),
     "upir_set_task_trace": (None, [_ctx_p, P(upir_task_trace)]),
     "upir_taskwait": (None, [_ctx_p, C.c_int32]),

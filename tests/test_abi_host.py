@@ -321,3 +321,22 @@ def test_status_strings():
     for s in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert U.lib().upir_strerror(s)
     assert U.upir_matmul_workspace_bytes(U.UPIR_BODY_MATMUL_SPLIT3, 4096, 4096, 4096) == 2 * 4096 * 4096 * 4
+
+
+def test_update_task_graph_and_validation(hctx):
+    """data_update tasks take part in the depend graph like loop tasks."""
+    h = hctx
+    lp = _cover_loop(h, 16)
+    X, Y = 0x100, 0x200
+    tid = C.c_int64()
+    arr = (U.upir_depend * 1)()
+    arr[0].addr, arr[0].type = X, U.UPIR_DEP_OUT
+    assert _status("upir_task_update", h, 0x5000, 64, U.UPIR_TO_DEVICE, arr, 1, C.byref(tid)) == U.UPIR_OK
+    assert tid.value == 0
+    assert _add_task(h, lp, [(X, U.UPIR_DEP_IN), (Y, U.UPIR_DEP_OUT)]) == 1
+    arr[0].addr, arr[0].type = Y, U.UPIR_DEP_IN
+    assert _status("upir_task_update", h, 0x5000, 64, U.UPIR_FROM_DEVICE, arr, 1, C.byref(tid)) == U.UPIR_OK
+    want = otasks.depend_edges([[(X, otasks.OUT)], [(X, otasks.IN), (Y, otasks.OUT)], [(Y, otasks.IN)]])
+    assert [_preds(h, j) for j in range(3)] == want == [[], [0], [1]]
+    assert _status("upir_task_update", h, 0x5000, 64, 9, None, 0, C.byref(tid)) == U.UPIR_EINVAL
+    assert _status("upir_task_update", h, None, 64, U.UPIR_TO_DEVICE, None, 0, C.byref(tid)) == U.UPIR_EINVAL

@@ -6,6 +6,7 @@ Bit-exact: AXPY outputs, MATVEC outputs between the two executors, tokens
 edge would change), coverage counts. Stamps: every edge i -> j has
 done[i] < start[j]. SUM results within 1e-5 * sum|x|, MATVEC normwise 1e-5.
 """
+import ctypes as C
 import sys
 
 import numpy as np
@@ -279,3 +280,76 @@ def test_taskloop_in_a_task_graph(ctx, mode):
         assert np.array_equal(ty.cpu().numpy(), bodies.axpy(2.5, a, b))
     for lp in lps:
         ctx.free(lp)
+
+
+# ------------------------------------------------ data_update as tasks ----
+
+def _pipeline(ctx, x, y, chunks, X0, Y0, trace=None):
+    """Per chunk: update(to) x_i, update(to) y_i, AXPY on the chunk,
+    update(from) y_i; edges only within a chunk."""
+    n = x.numel()
+    Cn = n // chunks
+    xp, yp = x.data_ptr(), y.data_ptr()
+    lps = []
+    for i in range(chunks):
+        Xi, Yi = X0 + 64 * i, Y0 + 64 * i
+        ctx.task_update(xp + 4 * i * Cn, 4 * Cn, U.UPIR_TO_DEVICE, [(Xi, U.UPIR_DEP_OUT)])
+        ctx.task_update(yp + 4 * i * Cn, 4 * Cn, U.UPIR_TO_DEVICE, [(Yi, U.UPIR_DEP_OUT)])
+        lp = ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, xp + 4 * i * Cn, yp + 4 * i * Cn), [(0, Cn, 1)],
+                      None, None, device_ptrs=False)
+        ctx.task(lp, [(Xi, U.UPIR_DEP_IN), (Yi, U.UPIR_DEP_INOUT)])
+        ctx.task_update(yp + 4 * i * Cn, 4 * Cn, U.UPIR_FROM_DEVICE, [(Yi, U.UPIR_DEP_IN)])
+        lps.append(lp)
+    return lps
+
+
+def test_update_tasks_pipeline_chunks(ctx):
+    """Host (pinned) arrays mapped with alloc; copies in, AXPY and copies out
+    as tasks over 8 chunks: the host result equals the oracle's AXPY and the
+    token chain (task order across the three queues) equals the oracle's."""
+    n, chunks = 1 << 22, 8
+    x0, y0 = synth.uniform_pm1(53, 0, n), synth.uniform_pm1(53, 1, n)
+    x = torch.from_numpy(x0).pin_memory()
+    y = torch.from_numpy(y0).pin_memory()
+    for t in (x, y):
+        U.upir_data_map(ctx.h, t.data_ptr(), 4 * n, U.UPIR_MAP_ALLOC, U.UPIR_ACCESS_RW, None)
+    lps = _pipeline(ctx, x, y, chunks, 0x10000, 0x20000)
+    ntask = 4 * chunks
+    deps = []
+    for i in range(chunks):
+        Xi, Yi = 0x10000 + 64 * i, 0x20000 + 64 * i
+        deps += [[(Xi, otasks.OUT)], [(Yi, otasks.OUT)], [(Xi, otasks.IN), (Yi, otasks.INOUT)], [(Yi, otasks.IN)]]
+    want_preds = otasks.depend_edges(deps)
+    assert [ctx.task_preds(j) for j in range(ntask)] == want_preds
+    tok = torch.zeros(ntask, dtype=torch.int64, device="cuda")
+    ctx.set_trace(tok.data_ptr())
+    y.zero_()  # the copies read y while the tasks run: reset the host value first
+    y.copy_(torch.from_numpy(y0))
+    ctx.taskwait(U.UPIR_TASKWAIT_PLAIN)
+    ctx.set_trace()
+    assert np.array_equal(y.numpy(), bodies.axpy(2.5, x0, y0))
+    got = [int(v) & (2 ** 64 - 1) for v in tok.cpu().numpy().tolist()]
+    assert got == otasks.tokens(want_preds)
+    # untraced run (overlapping queues) gives the same result
+    y.copy_(torch.from_numpy(y0))
+    _pipeline(ctx, x, y, chunks, 0x10000, 0x20000)
+    ctx.taskwait(U.UPIR_TASKWAIT_PLAIN)
+    assert np.array_equal(y.numpy(), bodies.axpy(2.5, x0, y0))
+    for t in (x, y):
+        U.upir_data_unmap(ctx.h, t.data_ptr(), U.UPIR_MAP_ALLOC)
+    for lp in lps:
+        ctx.free(lp)
+
+
+def test_update_tasks_rejected_where_unsupported(ctx):
+    v = torch.zeros(1024).pin_memory()
+    U.upir_data_map(ctx.h, v.data_ptr(), 4096, U.UPIR_MAP_ALLOC, U.UPIR_ACCESS_RW, None)
+    ctx.task_update(v.data_ptr(), 0, U.UPIR_TO_DEVICE)
+    assert U.raw("upir_taskwait")(ctx.h, U.UPIR_TASKWAIT_BATCHED) == U.UPIR_EUNSUPPORTED
+    g = C.c_void_p()
+    assert U.raw("upir_taskwait_graph")(ctx.h, U.UPIR_TASKWAIT_PLAIN, C.byref(g)) == U.UPIR_EUNSUPPORTED
+    ctx.taskwait(U.UPIR_TASKWAIT_PLAIN)                       # still pending: runs now
+    U.upir_data_unmap(ctx.h, v.data_ptr(), U.UPIR_MAP_ALLOC)
+    w = np.zeros(16, np.float32)                              # never mapped
+    ctx.task_update(w.ctypes.data, 64, U.UPIR_FROM_DEVICE)
+    assert U.raw("upir_taskwait")(ctx.h, U.UPIR_TASKWAIT_PLAIN) == U.UPIR_ENOTMAPPED
