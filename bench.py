@@ -1,6 +1,6 @@
 """Benchmark of the UPIR data-parallel loop library on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--configs 1,1L,0,2,3,4,P]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--configs 1,1L,0,2,3,4,P,D]
                     [--no-cpu-baseline]
 
 One step = one pass of the headline workload: a 4096 x 4096 float32 Jacobi
@@ -333,6 +333,55 @@ def bench_paper_grid(torch, ctx, reps=10):
     return out
 
 
+# ----------------------------------------- overlapped data movement (tasks)
+def bench_pipeline(torch, ctx, n=1 << 26, chunks=16, reps=3):
+    """AXPY on pinned host arrays (two 256 MiB vectors) through the device:
+    copy x and y in, compute, copy y out. Serial: one chunk (every step waits
+    for the previous). Pipelined: `chunks` chunks as data_update / loop tasks
+    with per-chunk depend edges, so copies in, compute and copies out of
+    different chunks overlap on the three queues. Times are wall-clock."""
+    x = synth.uniform_pm1_torch(80, 0, n, device="cuda").cpu().pin_memory()
+    y0 = synth.uniform_pm1_torch(80, 1, n, device="cuda").cpu()
+    y = y0.clone().pin_memory()
+    for t in (x, y):
+        U.upir_data_map(ctx.h, t.data_ptr(), 4 * n, U.UPIR_MAP_ALLOC, U.UPIR_ACCESS_RW, None)
+
+    def run(nc):
+        C_ = n // nc
+        xp, yp = x.data_ptr(), y.data_ptr()
+        lps = []
+        for i in range(nc):
+            Xi, Yi = 0x100000 + 64 * i, 0x200000 + 64 * i
+            ctx.task_update(xp + 4 * i * C_, 4 * C_, U.UPIR_TO_DEVICE, [(Xi, U.UPIR_DEP_OUT)])
+            ctx.task_update(yp + 4 * i * C_, 4 * C_, U.UPIR_TO_DEVICE, [(Yi, U.UPIR_DEP_OUT)])
+            lp = ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, xp + 4 * i * C_, yp + 4 * i * C_), [(0, C_, 1)],
+                          None, None, device_ptrs=False)
+            ctx.task(lp, [(Xi, U.UPIR_DEP_IN), (Yi, U.UPIR_DEP_INOUT)])
+            ctx.task_update(yp + 4 * i * C_, 4 * C_, U.UPIR_FROM_DEVICE, [(Yi, U.UPIR_DEP_IN)])
+            lps.append(lp)
+        t0 = time.perf_counter()
+        ctx.taskwait(U.UPIR_TASKWAIT_PLAIN)
+        dt = time.perf_counter() - t0
+        for lp in lps:
+            ctx.free(lp)
+        return dt
+
+    out = {}
+    for name, nc in (("serial", 1), ("pipelined", chunks)):
+        run(nc)  # warm-up
+        ts = []
+        for _ in range(reps):
+            y.copy_(y0)
+            ts.append(run(nc))
+        out[name + "_ms"] = round(1e3 * sorted(ts)[len(ts) // 2], 3)
+    for t in (x, y):
+        U.upir_data_unmap(ctx.h, t.data_ptr(), U.UPIR_MAP_ALLOC)
+    out.update({"n": n, "chunks": chunks, "bytes_moved": 12 * n,
+                "speedup": round(out["serial_ms"] / out["pipelined_ms"], 3),
+                "link_GBps_pipelined": round(12 * n / (out["pipelined_ms"] * 1e-3) / 1e9, 1)})
+    return out
+
+
 # ------------------------------------------------------------------ matmul
 def bench_matmul(torch, ctx, timer, reps=5):
     n = 4096
@@ -642,9 +691,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--configs", default="1,1L,0,2,3,4,P",
+    ap.add_argument("--configs", default="1,1L,0,2,3,4,P,D",
                     help="1 Jacobi 4096^2 (always timed: the headline), 1L Jacobi 16384^2, 0 AXPY+sum, "
-                         "2 matmul, 3 batched tasks, 4 learned schedule, P the paper's size grids")
+                         "2 matmul, 3 batched tasks, 4 learned schedule, P the paper's size grids, "
+                         "D overlapped data movement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (known bytes) to scale HBM counters")
@@ -708,6 +758,9 @@ def main():
     if "1L" in configs:
         log("jacobi 16384^2 (beyond the MALL)")
         extras["jacobi_16384"] = bench_jacobi_large(torch, ctx)
+    if "D" in configs:
+        log("overlapped data movement: data_update tasks with depend")
+        extras["pipeline_axpy"] = bench_pipeline(torch, ctx)
     if "P" in configs:
         log("the paper's size grids (AXPY, matvec, matmul, 7x7 stencil), host arrays")
         extras["paper_grid"] = bench_paper_grid(torch, ctx)
