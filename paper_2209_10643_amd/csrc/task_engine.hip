@@ -94,6 +94,22 @@ __device__ inline void cst2(float *p, float2 v) {
 }
 __device__ inline void cst(float *p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
+// 16-byte device-coherent accesses through a buffer resource over one tile's
+// range (cache policy sc1, the level the agent-scope atomics above use; the
+// resource's record count also bounds the accesses to the tile).
+typedef float f32x4e __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4e __attribute__((ext_vector_type(4)));
+constexpr int kCoherent = 16;  // sc1
+__device__ inline __amdgpu_buffer_rsrc_t tile_rsrc(const void *base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline f32x4e cld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(f32x4e, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kCoherent));
+}
+__device__ inline void cst4(__amdgpu_buffer_rsrc_t r, uint32_t off, f32x4e v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4e, v), r, off, 0, kCoherent);
+}
+
 // Reset the mutable engine state (a kernel, so graphs hold no memset node)
 // and lay out the tiles of the initially ready tasks at the front of the
 // work list.
@@ -114,18 +130,26 @@ __global__ void k_engine_reset(EngineD E) {
 }
 
 // One tile of a task, executed by the whole workgroup; `acc` collects this
-// lane's contribution to the task's reduction.
-__device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
+// lane's contribution to the task's reduction. OP (the task's reduction, or
+// RED_NONE) is a template constant so the per-element fold is one
+// instruction; several chunks (rows for MATVEC) are loaded before any is
+// used, to keep loads in flight.
+template <int OP>
+__device__ inline void fold_op(float &acc, float v) {
+  if (OP != RED_NONE) acc = red_apply(OP, acc, v);
+}
+
+template <int OP>
+__device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
+  constexpr int UN = 4;
   const int64_t lo = tile * t.tile;
   const int64_t hi = lo + t.tile < t.n ? lo + t.tile : t.n;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int op = t.red_op;
   if (t.kind == UPIR_BODY_MATVEC) {
     // same arithmetic as the loop kernel's row: lane l takes columns
     // 4l .. 4l+3 of each 256-column block in order, then a fixed butterfly
     const int lane = tid % WAVE, w = tid / WAVE, nw = nt / WAVE;
-    for (int64_t k = lo + w; k < hi; k += nw) {
-      const int64_t r = t.lb + k * t.step;
+    auto row_dot = [&](int64_t r) {
       const float *a = t.A + r * t.lda;
       float s = 0.0f;
       for (int64_t c0 = 0; c0 < t.cols; c0 += 256) {
@@ -141,10 +165,39 @@ __device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
             if (c + q < t.cols) s = __builtin_fmaf(cld(a + c + q), cld(t.x + c + q), s);
         }
       }
-      s = wave_reduce(RED_SUM, s);
+      return s;
+    };
+    int64_t k = lo + w;
+    if (t.vec && t.cols == 256 && t.step == 1 && 4 * (hi - lo) * t.lda < (1LL << 31)) {
+      // the common shape: four rows in flight per wavefront
+      const int c = 4 * lane;
+      const float2 x0 = cld2(t.x + c), x1 = cld2(t.x + c + 2);
+      const __amdgpu_buffer_rsrc_t ra = tile_rsrc(t.A + (t.lb + lo) * t.lda, 4 * (hi - lo) * t.lda);
+      for (; k + (UN - 1) * nw < hi; k += UN * nw) {
+        f32x4e av[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) av[u] = cld4(ra, (uint32_t)(4 * ((k + u * nw - lo) * t.lda + c)));
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+          float s = 0.0f;
+          s = __builtin_fmaf(av[u].x, x0.x, s);
+          s = __builtin_fmaf(av[u].y, x0.y, s);
+          s = __builtin_fmaf(av[u].z, x1.x, s);
+          s = __builtin_fmaf(av[u].w, x1.y, s);
+          s = wave_reduce(RED_SUM, s);
+          if (lane == 0) {
+            cst(t.y + t.lb + k + u * nw, s);
+            fold_op<OP>(acc, s);
+          }
+        }
+      }
+    }
+    for (; k < hi; k += nw) {
+      const int64_t r = t.lb + k * t.step;
+      const float s = wave_reduce(RED_SUM, row_dot(r));
       if (lane == 0) {
         cst(t.y + r, s);
-        if (op) acc = red_apply(op, acc, s);
+        fold_op<OP>(acc, s);
       }
     }
     return;
@@ -152,36 +205,66 @@ __device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
   if (t.vec) {  // unit step, 16-byte aligned start of every tile
     const int64_t b = t.lb + lo;
     const int64_t len = hi - lo, nc = len >> 2;
+    int64_t m = tid;
     if (t.kind == UPIR_BODY_AXPY) {
-      for (int64_t m = tid; m < nc; m += nt) {
-        const float *xp = t.x + b + 4 * m;
-        float *yp = t.y + b + 4 * m;
-        const float2 x0 = cld2(xp), x1 = cld2(xp + 2), y0 = cld2(yp), y1 = cld2(yp + 2);
-        float2 r0, r1;
-        r0.x = __builtin_fmaf(t.a, x0.x, y0.x);
-        r0.y = __builtin_fmaf(t.a, x0.y, y0.y);
-        r1.x = __builtin_fmaf(t.a, x1.x, y1.x);
-        r1.y = __builtin_fmaf(t.a, x1.y, y1.y);
-        cst2(yp, r0);
-        cst2(yp + 2, r1);
-        if (op) {
-          acc = red_apply(op, acc, r0.x);
-          acc = red_apply(op, acc, r0.y);
-          acc = red_apply(op, acc, r1.x);
-          acc = red_apply(op, acc, r1.y);
+      const __amdgpu_buffer_rsrc_t rx = tile_rsrc(t.x + b, 16 * nc), ry = tile_rsrc(t.y + b, 16 * nc);
+      for (; m + (UN - 1) * nt < nc; m += UN * nt) {
+        f32x4e xv[UN], yv[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+          xv[u] = cld4(rx, (uint32_t)(16 * (m + u * nt)));
+          yv[u] = cld4(ry, (uint32_t)(16 * (m + u * nt)));
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+          f32x4e r;
+          r.x = __builtin_fmaf(t.a, xv[u].x, yv[u].x);
+          r.y = __builtin_fmaf(t.a, xv[u].y, yv[u].y);
+          r.z = __builtin_fmaf(t.a, xv[u].z, yv[u].z);
+          r.w = __builtin_fmaf(t.a, xv[u].w, yv[u].w);
+          cst4(ry, (uint32_t)(16 * (m + u * nt)), r);
+          fold_op<OP>(acc, r.x);
+          fold_op<OP>(acc, r.y);
+          fold_op<OP>(acc, r.z);
+          fold_op<OP>(acc, r.w);
         }
       }
+      for (; m < nc; m += nt) {
+        const f32x4e xv = cld4(rx, (uint32_t)(16 * m)), yv = cld4(ry, (uint32_t)(16 * m));
+        f32x4e r;
+        r.x = __builtin_fmaf(t.a, xv.x, yv.x);
+        r.y = __builtin_fmaf(t.a, xv.y, yv.y);
+        r.z = __builtin_fmaf(t.a, xv.z, yv.z);
+        r.w = __builtin_fmaf(t.a, xv.w, yv.w);
+        cst4(ry, (uint32_t)(16 * m), r);
+        fold_op<OP>(acc, r.x);
+        fold_op<OP>(acc, r.y);
+        fold_op<OP>(acc, r.z);
+        fold_op<OP>(acc, r.w);
+      }
     } else if (t.kind == UPIR_BODY_SUM) {
-      for (int64_t m = tid; m < nc; m += nt) {
-        const float *xp = t.x + b + 4 * m;
-        const float2 x0 = cld2(xp), x1 = cld2(xp + 2);
-        acc = red_apply(op, acc, x0.x);
-        acc = red_apply(op, acc, x0.y);
-        acc = red_apply(op, acc, x1.x);
-        acc = red_apply(op, acc, x1.y);
+      const __amdgpu_buffer_rsrc_t rx = tile_rsrc(t.x + b, 16 * nc);
+      for (; m + (2 * UN - 1) * nt < nc; m += 2 * UN * nt) {
+        f32x4e xv[2 * UN];
+#pragma unroll
+        for (int u = 0; u < 2 * UN; ++u) xv[u] = cld4(rx, (uint32_t)(16 * (m + u * nt)));
+#pragma unroll
+        for (int u = 0; u < 2 * UN; ++u) {
+          fold_op<OP>(acc, xv[u].x);
+          fold_op<OP>(acc, xv[u].y);
+          fold_op<OP>(acc, xv[u].z);
+          fold_op<OP>(acc, xv[u].w);
+        }
+      }
+      for (; m < nc; m += nt) {
+        const f32x4e xv = cld4(rx, (uint32_t)(16 * m));
+        fold_op<OP>(acc, xv.x);
+        fold_op<OP>(acc, xv.y);
+        fold_op<OP>(acc, xv.z);
+        fold_op<OP>(acc, xv.w);
       }
     } else {
-      for (int64_t m = tid; m < nc; m += nt)
+      for (; m < nc; m += nt)
         for (int q = 0; q < 4; ++q) atomicAdd(&t.cnt[lo + 4 * m + q], 1);
     }
     for (int64_t k = lo + 4 * nc + tid; k < hi; k += nt) {  // ragged end of the tile
@@ -189,9 +272,9 @@ __device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
       if (t.kind == UPIR_BODY_AXPY) {
         const float r = __builtin_fmaf(t.a, cld(t.x + i), cld(t.y + i));
         cst(t.y + i, r);
-        if (op) acc = red_apply(op, acc, r);
+        fold_op<OP>(acc, r);
       } else if (t.kind == UPIR_BODY_SUM) {
-        acc = red_apply(op, acc, cld(t.x + i));
+        fold_op<OP>(acc, cld(t.x + i));
       } else {
         atomicAdd(&t.cnt[k], 1);
       }
@@ -203,12 +286,21 @@ __device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
     if (t.kind == UPIR_BODY_AXPY) {
       const float r = __builtin_fmaf(t.a, cld(t.x + i), cld(t.y + i));
       cst(t.y + i, r);
-      if (op) acc = red_apply(op, acc, r);
+      fold_op<OP>(acc, r);
     } else if (t.kind == UPIR_BODY_SUM) {
-      acc = red_apply(op, acc, cld(t.x + i));
+      fold_op<OP>(acc, cld(t.x + i));
     } else {
       atomicAdd(&t.cnt[k], 1);
     }
+  }
+}
+
+__device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
+  switch (t.red_op) {
+    case RED_SUM: return run_tile_op<RED_SUM>(t, tile, acc);
+    case RED_MAX: return run_tile_op<RED_MAX>(t, tile, acc);
+    case RED_MIN: return run_tile_op<RED_MIN>(t, tile, acc);
+    default: return run_tile_op<RED_NONE>(t, tile, acc);
   }
 }
 
@@ -429,7 +521,7 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
     }
     int64_t tile = task_tile(c, lp);
     if (lp->kind != UPIR_BODY_MATVEC) tile = std::max<int64_t>(4, (tile + 3) / 4 * 4);
-    d.tile = std::max<int64_t>(1, tile);
+    d.tile = std::max<int64_t>(1, std::min<int64_t>(tile, 1 << 24));  // tile bytes fit a buffer resource
     const int64_t nt = std::max<int64_t>(1, (d.n + d.tile - 1) / d.tile);
     if (nt > (1LL << 30)) return upir_fail(c, UPIR_EINVAL, "task %d has too many tiles", j);
     d.ntiles = (int32_t)nt;
