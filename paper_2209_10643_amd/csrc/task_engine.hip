@@ -410,7 +410,9 @@ __global__ void k_zero_u64(unsigned long long *p) { *p = 0ULL; }
 
 using namespace upir;
 
-static int64_t default_task_tile(int32_t kind) { return kind == UPIR_BODY_MATVEC ? 256 : 65536; }
+// 16384 elements (64 KiB of each array) or 64 matvec rows: enough work per tile to
+// stream, small enough that the tiles of a long task spread over the chip
+static int64_t default_task_tile(int32_t kind) { return kind == UPIR_BODY_MATVEC ? 64 : 16384; }
 
 // tile size of a task: the schedule's tile[0] if given, else the default
 static int64_t task_tile(upir_ctx *, upir_loop_obj *lp) {
