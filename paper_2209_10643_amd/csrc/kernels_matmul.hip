@@ -52,15 +52,96 @@ __global__ void __launch_bounds__(256) k_split_cols(const float *__restrict__ B,
   }
 }
 
+// Vector forms (K % 8 == 0, 16-byte aligned rows): eight consecutive k per
+// thread, two 16-byte loads and one 16-byte store of eight bfloat16 per
+// output array.
+typedef float f32x4s __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4s __attribute__((ext_vector_type(4)));
+__device__ inline unsigned pack2(uint16_t a, uint16_t b) { return (unsigned)a | ((unsigned)b << 16); }
+
+__global__ void __launch_bounds__(256) k_split_rows8(const float *__restrict__ A, int64_t M, int64_t K, int64_t lda,
+                                                     uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+  const int64_t chunks = M * (K / 8);
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < chunks; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = 8 * c, i = e / K, k = e - i * K;
+    const f32x4s v0 = *(const f32x4s *)(A + i * lda + k), v1 = *(const f32x4s *)(A + i * lda + k + 4);
+    const float x[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    uint16_t h[8], l[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      h[q] = to_bf16_rne(x[q]);
+      l[q] = to_bf16_rne(x[q] - bf16f(h[q]));
+    }
+    *(u32x4s *)(hi + e) = u32x4s{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+    if (lo) *(u32x4s *)(lo + e) = u32x4s{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+  }
+}
+
+// B (K x N) -> N x K through a 64 (k) x 64 (n) LDS tile: rows of B are read
+// as float4, each output row n gets its 64 k as eight 16-byte stores.
+__global__ void __launch_bounds__(256) k_split_cols8(const float *__restrict__ B, int64_t K, int64_t N, int64_t ldb,
+                                                     uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+  __shared__ float t[64][65];
+  const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+  for (int q = threadIdx.x; q < 64 * 16; q += 256) {  // 64 rows x 16 float4
+    const int r = q / 16, c4 = 4 * (q % 16);
+    const int64_t k = k0 + r, n = n0 + c4;
+    f32x4s v = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (k < K && n + 3 < N) {
+      v = *(const f32x4s *)(B + k * ldb + n);
+    } else if (k < K) {
+      float e[4];
+      for (int j = 0; j < 4; ++j) e[j] = n + j < N ? B[k * ldb + n + j] : 0.0f;
+      v = f32x4s{e[0], e[1], e[2], e[3]};
+    }
+    t[r][c4] = v.x;
+    t[r][c4 + 1] = v.y;
+    t[r][c4 + 2] = v.z;
+    t[r][c4 + 3] = v.w;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 64 * 8; q += 256) {  // 64 output rows x 8 chunks of 8 k
+    const int r = q / 8, kc = 8 * (q % 8);
+    const int64_t n = n0 + r, k = k0 + kc;
+    if (n >= N || k >= K) continue;  // K % 8 == 0: a chunk is all in or all out
+    uint16_t h[8], l[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float x = t[kc + j][r];
+      h[j] = to_bf16_rne(x);
+      l[j] = to_bf16_rne(x - bf16f(h[j]));
+    }
+    *(u32x4s *)(hi + n * K + k) = u32x4s{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+    if (lo) *(u32x4s *)(lo + n * K + k) = u32x4s{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+  }
+}
+
 hipError_t launch_bf16_split(const MatmulP &p, bool need_lo, hipStream_t st) {
+  // vector forms: K % 8 == 0, 16-byte aligned operands and rows, aligned workspace
+  const bool ws_ok = (uintptr_t)p.ah % 16 == 0 && (uintptr_t)p.bh % 16 == 0 &&
+                     (!need_lo || ((uintptr_t)p.al % 16 == 0 && (uintptr_t)p.bl % 16 == 0));
+  const bool vec = p.K % 8 == 0 && ws_ok;
+  const bool vec_a = vec && p.lda % 4 == 0 && (uintptr_t)p.A % 16 == 0;
+  const bool vec_b = vec && p.ldb % 4 == 0 && (uintptr_t)p.B % 16 == 0;
   if (p.M > 0 && p.K > 0) {
-    const int64_t tot = p.M * p.K;
-    const int g = (int)std::min<int64_t>((tot + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_split_rows, dim3(g), dim3(256), 0, st, p.A, p.M, p.K, p.lda, p.ah, need_lo ? p.al : nullptr);
+    if (vec_a) {
+      const int64_t chunks = p.M * (p.K / 8);
+      const int g = (int)std::min<int64_t>((chunks + 255) / 256, 16384);
+      hipLaunchKernelGGL(k_split_rows8, dim3(g), dim3(256), 0, st, p.A, p.M, p.K, p.lda, p.ah,
+                         need_lo ? p.al : nullptr);
+    } else {
+      const int64_t tot = p.M * p.K;
+      const int g = (int)std::min<int64_t>((tot + 255) / 256, 8192);
+      hipLaunchKernelGGL(k_split_rows, dim3(g), dim3(256), 0, st, p.A, p.M, p.K, p.lda, p.ah,
+                         need_lo ? p.al : nullptr);
+    }
   }
   if (p.N > 0 && p.K > 0) {
     dim3 g((unsigned)((p.N + 63) / 64), (unsigned)((p.K + 63) / 64));
-    hipLaunchKernelGGL(k_split_cols, g, dim3(256), 0, st, p.B, p.K, p.N, p.ldb, p.bh, need_lo ? p.bl : nullptr);
+    if (vec_b)
+      hipLaunchKernelGGL(k_split_cols8, g, dim3(256), 0, st, p.B, p.K, p.N, p.ldb, p.bh, need_lo ? p.bl : nullptr);
+    else
+      hipLaunchKernelGGL(k_split_cols, g, dim3(256), 0, st, p.B, p.K, p.N, p.ldb, p.bh, need_lo ? p.bl : nullptr);
   }
   return hipGetLastError();
 }
