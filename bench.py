@@ -219,7 +219,51 @@ def bench_axpy(torch, ctx, timer, reps=1000):
     for h in (lp, lb, ls):
         ctx.free(h)
     del xb, yb
+    out["sweep"] = axpy_sum_sweep(torch, ctx)
     return out
+
+
+def axpy_sum_sweep(torch, ctx, reps=10):
+    """AXPY + sum and SUM alone for n = 2^20 .. 2^28, one launch per sample
+    (HIP events around each). warm: back-to-back launches on resident data;
+    cold: a 512 MiB buffer is written between launches, so the operands come
+    from HBM. Mean, median and best (the shortest launch) in GB/s of
+    algorithmic bytes."""
+    scrub = torch.empty(1 << 27, dtype=torch.float32, device="cuda")
+    rows = []
+    for lg in (20, 22, 24, 26, 28):
+        n = 1 << lg
+        x = synth.uniform_pm1_torch(2, 0, n, device="cuda")
+        y = synth.uniform_pm1_torch(2, 1, n, device="cuda")
+        r = torch.zeros(1, dtype=torch.float64, device="cuda")
+        la = ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, x.data_ptr(), y.data_ptr()), [(0, n, 1)], None,
+                      H.make_red(U.UPIR_RED_SUM, r.data_ptr()))
+        ls = ctx.loop(U.UPIR_BODY_SUM, U.upir_sum_args(x.data_ptr(), U.UPIR_DT_F32, 0), [(0, n, 1)], None,
+                      H.make_red(U.UPIR_RED_SUM, r.data_ptr()))
+        row = {"n": n}
+        for name, lp, bpe in (("axpy_sum", la, 12), ("sum", ls, 4)):
+            for mode in ("warm", "cold"):
+                ctx.launch(lp)
+                ts = []
+                for _ in range(reps):
+                    if mode == "cold":
+                        scrub.fill_(1.0)
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    ctx.launch(lp)
+                    b.record()
+                    b.synchronize()
+                    ts.append(a.elapsed_time(b))
+                g = [bpe * n / (t * 1e-3) / 1e9 for t in ts]
+                row[f"{name}_{mode}_GBps"] = {"mean": round(float(np.mean(g)), 1), "median": round(float(np.median(g)), 1),
+                                              "best": round(float(np.max(g)), 1)}
+        rows.append(row)
+        ctx.free(la)
+        ctx.free(ls)
+        del x, y
+    del scrub
+    torch.cuda.empty_cache()
+    return rows
 
 
 # ------------------------------------------------- the paper's size grids

@@ -223,9 +223,8 @@ hipError_t launch_generic(int32_t body, const void *payload, const LoopK &L, con
 // team U + unit, exactly the static-chunk-4 schedule. x and y point at the
 // element of the first iteration and are 16-byte aligned. Four owned chunks
 // of each input (eight for SUM) are loaded before any is used to keep
-// several loads in flight. NT: the
-// arrays are larger than the last-level cache, so loads and stores carry the
-// non-temporal hint (streamed through, not kept).
+// several loads in flight. NT: loads and stores carry the non-temporal hint
+// (streamed through rather than kept).
 template <bool NT>
 __device__ __forceinline__ f32x4 ld4(const f32x4 *p) {
   if (NT) return __builtin_nontemporal_load(p);
@@ -337,8 +336,11 @@ static void go_stream4_op(bool nt, dim3 g, dim3 b, hipStream_t st, int64_t n, fl
 
 hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, const SchedK &S, const RedK &R,
                           hipStream_t st) {
-  // beyond the 256 MB last-level cache the arrays cannot stay resident
-  const bool nt = (uint64_t)L.n * (body == 1 ? 8u : 4u) > (256ull << 20);
+  // From 64 MiB of operands on, loads and stores carry the non-temporal hint:
+  // measured on MI355X it lifts cold-cache streams by 40-120% and costs at
+  // most 6% when the operands are still resident in the 256 MB last-level
+  // cache; below 64 MiB plain accesses are as fast or faster either way.
+  const bool nt = (uint64_t)L.n * (body == 1 ? 8u : 4u) >= (64ull << 20);
   const int64_t n = L.n, lb = L.lb[0];
   dim3 g(S.T), b(S.U);
   if (body == 1) {

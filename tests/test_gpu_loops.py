@@ -83,8 +83,8 @@ def test_axpy_sum_parity(ctx, n, sched, spmd):
 
 
 def test_stream_beyond_last_level_cache(ctx):
-    """Arrays larger than the 256 MB last-level cache take the non-temporal
-    streaming kernel: AXPY + sum at n = 40M + 3, SUM body at n = 70M + 1."""
+    """Large operands (>= 64 MiB) take the non-temporal streaming kernel:
+    AXPY + sum at n = 40M + 3, SUM body at n = 70M + 1."""
     n = 40_000_003
     x, y = synth.uniform_pm1(21, 0, n), synth.uniform_pm1(21, 1, n)
     got_y, got_s, v = run_axpy(ctx, x, y, 2.5, [(0, n, 1)])
