@@ -497,3 +497,41 @@ def test_matmul_integer_exact(ctx):
         ctx.sync()
         assert np.array_equal(tC.cpu().numpy().astype(np.float64), want)
         ctx.free(lp)
+
+
+def test_jacobi_full_size_benchmark_configuration(ctx):
+    """The benchmark's workload at full size: 4096 x 4096, zero boundary,
+    interior uniform [0, 1), 100 sweeps as one captured graph with async
+    (deferred-fold) max residuals, in the tuned launch configuration the
+    benchmark times (tile 64 x 256, 256 units). Grid and all 100 residuals
+    bit-exact against the oracle."""
+    N, sweeps = 4096, 100
+    u0 = jacobi_grid(N, N, seed=12345)
+    a, b = dev(u0), dev(u0)
+    res = torch.zeros(sweeps, dtype=torch.float64, device="cuda")
+    sched = H.make_sched(U.UPIR_SCHED_STATIC, tile=(64, 256))
+    spmd = H.make_spmd(0, 256)
+    hs = []
+    for k in range(sweeps):
+        src, dst = (a, b) if k % 2 == 0 else (b, a)
+        hs.append(ctx.loop(U.UPIR_BODY_JACOBI5, U.upir_jacobi5_args(src.data_ptr(), dst.data_ptr(), N),
+                           [(1, N - 1, 1), (1, N - 1, 1)], sched,
+                           H.make_red(U.UPIR_RED_MAX, res[k:].data_ptr(), async_=True)))
+    assert U.VARIANTS[ctx.resolve(hs[0], spmd)[2]] == "jacobi_tile"
+    ctx.launch(hs, spmd)
+    ctx.sync()
+    a.copy_(dev(u0))
+    b.copy_(dev(u0))
+    res.zero_()
+    torch.cuda.synchronize()
+    ctx.graph_begin()
+    ctx.launch(hs, spmd)
+    g = ctx.graph_end()
+    ctx.graph_launch(g)
+    ctx.sync()
+    want_u, want_r = bodies.jacobi5(u0, sweeps)
+    assert np.array_equal(a.cpu().numpy(), want_u)
+    assert np.array_equal(res.cpu().numpy(), want_r)
+    ctx.graph_destroy(g)
+    for h in hs:
+        ctx.free(h)
