@@ -66,10 +66,10 @@ class Timer:
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB copy), bytes,
 # from profiles/jacobi5_4096_hbm_traffic.md. Valid for the kernel as profiled.
 JACOBI_4096_TRAFFIC = {
-    (8, 64): 136573607, (8, 128): 135273284, (8, 256): 135312345, (8, 512): 135755561,
-    (16, 64): 143492386, (16, 128): 136346974, (16, 256): 135122245, (16, 512): 135281860,
-    (32, 64): 139630302, (32, 128): 143322352, (32, 256): 136678686, (32, 512): 135143642,
-    (64, 64): 137468424, (64, 128): 140208840, (64, 256): 143366284, (64, 512): 136320995,
+    (8, 64): 136757042, (8, 128): 135225200, (8, 256): 135256335, (8, 512): 135733428,
+    (16, 64): 143558266, (16, 128): 136708351, (16, 256): 135172601, (16, 512): 135313486,
+    (32, 64): 139536320, (32, 128): 143362125, (32, 256): 137277107, (32, 512): 135129300,
+    (64, 64): 137456653, (64, 128): 139608978, (64, 256): 143415062, (64, 512): 136613626,
 }
 
 
