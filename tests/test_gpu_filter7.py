@@ -29,9 +29,13 @@ def note(*a):
 def ctx():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     U.lib()
-    c = H.Context(0)
+    s = torch.cuda.Stream()
+    prev = torch.cuda.current_stream()
+    torch.cuda.set_stream(s)  # torch's work and the library's are ordered on one stream
+    c = H.Context(0, stream=s)
     yield c
     c.close()
+    torch.cuda.set_stream(prev)
 
 
 def dev(a):
@@ -65,6 +69,9 @@ CASES = [
     ((203, 780), H.make_sched(U.UPIR_SCHED_STATIC, tile=(64, 256)), H.make_spmd(0, 512), "filter7_tile"),
     ((203, 780), H.make_sched(U.UPIR_SCHED_STATIC, tile=(32, 256)), H.make_spmd(5, 128), "filter7_tile"),
     ((203, 780), H.make_sched(U.UPIR_SCHED_STATIC_CHUNK, 3, tile=(8, 256)), H.make_spmd(4, 256), "filter7_tile"),
+    ((7, 8), None, None, "filter7_tile"),                                      # one output row of two points
+    ((7, 1028), None, None, "filter7_tile"),                                   # one output row
+    ((500, 8), None, None, "filter7_tile"),                                    # two output columns
     ((70, 77), None, None, "generic"),                                         # pitch % 4 != 0
     ((90, 100), H.make_sched(U.UPIR_SCHED_STATIC), H.make_spmd(9, 64), "generic"),
     ((90, 100), H.make_sched(U.UPIR_SCHED_DYNAMIC, 2), H.make_spmd(7, 64), "dynamic"),

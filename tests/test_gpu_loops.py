@@ -30,9 +30,13 @@ def note(*a):
 def ctx():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     U.lib()
-    c = H.Context(0)
+    s = torch.cuda.Stream()
+    prev = torch.cuda.current_stream()
+    torch.cuda.set_stream(s)  # torch's work and the library's are ordered on one stream
+    c = H.Context(0, stream=s)
     yield c
     c.close()
+    torch.cuda.set_stream(prev)
 
 
 def dev(a):
@@ -291,6 +295,9 @@ def run_jacobi(ctx, u0, sweeps, sched, spmd=None, graph=False, replays=1, op=Non
 
 JACOBI_CASES = [
     ((5, 7), None, None, "generic"),
+    ((3, 4), None, None, "jacobi_tile"),                   # one interior row of two points
+    ((3, 1028), None, None, "jacobi_tile"),                # one interior row
+    ((1000, 4), None, None, "jacobi_tile"),                # a thin column
     ((33, 65), None, None, "generic"),                     # ld % 4 != 0 -> generic path
     ((64, 64), None, None, "jacobi_tile"),
     ((260, 1028), None, None, "jacobi_tile"),              # ragged tiles in both directions
@@ -535,3 +542,40 @@ def test_jacobi_full_size_benchmark_configuration(ctx):
     ctx.graph_destroy(g)
     for h in hs:
         ctx.free(h)
+
+
+def test_axpy_beyond_int32_indices(ctx):
+    """n = 2^31 + 17 (16 GiB of operands): 64-bit iteration indices through
+    the non-temporal streaming kernel. Outputs at 2,000 sampled indices and
+    around the 2^31 boundary are bit-exact against the oracle computed on
+    those elements; the float64 sum is checked against an independent
+    float64 reduction of the outputs (torch) within the float sum bound."""
+    n = (1 << 31) + 17
+    note(f"axpy n={n}")
+    x = torch.empty(n, device="cuda")
+    y = torch.empty(n, device="cuda")
+    c = 1 << 28
+    for s0 in range(0, n, c):
+        m = min(c, n - s0)
+        x[s0:s0 + m] = synth.uniform_pm1_torch(61, 0, m, start=s0, device="cuda")
+        y[s0:s0 + m] = synth.uniform_pm1_torch(61, 1, m, start=s0, device="cuda")
+    torch.cuda.synchronize()  # the library runs on its own stream
+    r = dbl()
+    lp = ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, x.data_ptr(), y.data_ptr()), [(0, n, 1)], None,
+                  H.make_red(U.UPIR_RED_SUM, r.data_ptr()))
+    assert U.VARIANTS[ctx.resolve(lp)[2]] == "stream4"
+    ctx.launch(lp)
+    ctx.sync()
+    rng = np.random.default_rng(61)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 2000), [0, 1, (1 << 31) - 2, (1 << 31) - 1, 1 << 31,
+                                                                   (1 << 31) + 1, n - 2, n - 1]]))
+    got = y[torch.from_numpy(idx).cuda()].cpu().numpy()
+    xs = np.array([synth.uniform_pm1(61, 0, 1, start=int(i))[0] for i in idx], np.float32)
+    ys = np.array([synth.uniform_pm1(61, 1, 1, start=int(i))[0] for i in idx], np.float32)
+    assert np.array_equal(got, bodies.axpy(2.5, xs, ys))
+    want_s = float(y.double().sum().item())
+    abs_s = float(y.double().abs().sum().item())
+    assert abs(r.item() - want_s) <= 1e-5 * abs_s
+    ctx.free(lp)
+    del x, y
+    torch.cuda.empty_cache()

@@ -32,9 +32,13 @@ def note(*a):
 def ctx():
     assert torch.cuda.is_available()
     U.lib()
-    c = H.Context(0)
+    s = torch.cuda.Stream()
+    prev = torch.cuda.current_stream()
+    torch.cuda.set_stream(s)  # torch's work and the library's are ordered on one stream
+    c = H.Context(0, stream=s)
     yield c
     c.close()
+    torch.cuda.set_stream(prev)
 
 
 def run_mm(ctx, kind, A, B, sched=None, spmd=None):
