@@ -781,7 +781,7 @@ def main():
     for _ in range(args.steps):
         jw.step()
     b.record(stream)
-    b.synchronize()
+    torch.cuda.synchronize()  # one GPU: the barrier is the device synchronisation
     ms_step = a.elapsed_time(b) / args.steps
     step_bytes = jw.SWEEPS * jw.bytes_per_sweep()
     value = step_bytes / (ms_step * 1e-3) / 1e9
