@@ -14,6 +14,8 @@
  *   upir_data_*           sec. 4    data mapping to/from/tofrom/allocate,
  *                                   explicit data_update, mm allocator hook
  *   upir_task / taskwait  sec. 3.3  offloaded tasks ordered by depend; taskwait
+ *   upir_taskloop         sec. 3.2  taskloop(grainsize, num_tasks) over the tasks
+ *   upir_task_update      sec. 4    data_update with depend, as a copy task
  *
  * There is no compiler here to outline user code, so a loop body is one of
  * a closed set of built-in bodies (upir_body_kind). Loops and reductions run
@@ -72,7 +74,8 @@ upir_status upir_init(int device, void *hip_stream, upir_ctx **out);
 upir_status upir_finalize(upir_ctx *ctx);
 const char *upir_strerror(upir_status s);
 const char *upir_last_error(const upir_ctx *ctx);
-/* Block until all work enqueued on the context's stream has finished. */
+/* Run a deferred (async) reduction fold if one is pending, then block until
+ * all work enqueued on the context's stream has finished. */
 upir_status upir_sync(upir_ctx *ctx);
 /* Library version string. */
 const char *upir_version(void);
