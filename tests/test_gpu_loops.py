@@ -579,3 +579,26 @@ def test_axpy_beyond_int32_indices(ctx):
     ctx.free(lp)
     del x, y
     torch.cuda.empty_cache()
+
+
+def test_stencils_with_empty_interior(ctx):
+    """Grids too small for an interior: nothing is written, a reduction
+    returns its init."""
+    u = np.arange(4, dtype=np.float32).reshape(2, 2)
+    a, b = dev(u), dev(np.full((2, 2), -1.0, np.float32))
+    r = dbl()
+    lp = ctx.loop(U.UPIR_BODY_JACOBI5, U.upir_jacobi5_args(a.data_ptr(), b.data_ptr(), 2), [(1, 1, 1), (1, 1, 1)],
+                  None, H.make_red(U.UPIR_RED_MAX, r.data_ptr(), init=0.5))
+    ctx.launch(lp)
+    ctx.sync()
+    assert (b.cpu().numpy() == -1.0).all() and r.item() == 0.5
+    ctx.free(lp)
+    s6 = dev(np.ones((6, 8), np.float32))
+    d6 = dev(np.full((6, 8), -1.0, np.float32))
+    w = dev(np.ones(49, np.float32))
+    lf = ctx.loop(U.UPIR_BODY_FILTER7, U.upir_filter7_args(s6.data_ptr(), d6.data_ptr(), w.data_ptr(), 8),
+                  [(3, 3, 1), (3, 5, 1)])
+    ctx.launch(lf)
+    ctx.sync()
+    assert (d6.cpu().numpy() == -1.0).all()
+    ctx.free(lf)

@@ -119,3 +119,30 @@ def test_mfma_full_size_4096(ctx, kind):
         ref = bodies.matmul_entry(A, B, i, j)
         scale = float(np.abs(A[i].astype(np.float64)) @ np.abs(B[:, j].astype(np.float64)))
         assert abs(got[i, j] - ref) <= 8 * TOL[kind] * scale
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16", "split"])
+def test_empty_reduction_dimension_gives_zero(ctx, kind):
+    """K = 0: every entry of C is the empty sum, 0."""
+    M, N = 64, 96
+    tA = torch.zeros(M, 4, device="cuda")
+    tB = torch.zeros(4, N, device="cuda")
+    tC = torch.full((M, N), float("nan"), device="cuda")
+    args = U.upir_matmul_args(tA.data_ptr(), tB.data_ptr(), tC.data_ptr(), 0, 4, N, N, None, 0)
+    lp = ctx.loop(KINDS[kind], args, [(0, M, 1), (0, N, 1)])
+    ctx.launch(lp)
+    ctx.sync()
+    assert (tC.cpu().numpy() == 0).all()
+    ctx.free(lp)
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16"])
+def test_empty_output_writes_nothing(ctx, kind):
+    tA = torch.ones(8, 8, device="cuda")
+    tC = torch.full((8, 8), -3.0, device="cuda")
+    args = U.upir_matmul_args(tA.data_ptr(), tA.data_ptr(), tC.data_ptr(), 8, 8, 8, 8, None, 0)
+    lp = ctx.loop(KINDS[kind], args, [(0, 0, 1), (0, 8, 1)])
+    ctx.launch(lp)
+    ctx.sync()
+    assert (tC.cpu().numpy() == -3.0).all()
+    ctx.free(lp)
