@@ -66,10 +66,10 @@ class Timer:
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB copy), bytes,
 # from profiles/jacobi5_4096_hbm_traffic.md. Valid for the kernel as profiled.
 JACOBI_4096_TRAFFIC = {
-    (8, 64): 136757042, (8, 128): 135225200, (8, 256): 135256335, (8, 512): 135733428,
-    (16, 64): 143558266, (16, 128): 136708351, (16, 256): 135172601, (16, 512): 135313486,
-    (32, 64): 139536320, (32, 128): 143362125, (32, 256): 137277107, (32, 512): 135129300,
-    (64, 64): 137456653, (64, 128): 139608978, (64, 256): 143415062, (64, 512): 136613626,
+    (8, 64): 135425454, (8, 128): 135207870, (8, 256): 135284897, (8, 512): 135737564,
+    (16, 64): 143530218, (16, 128): 135341068, (16, 256): 135049807, (16, 512): 135252386,
+    (32, 64): 139607244, (32, 128): 143496751, (32, 256): 135212857, (32, 512): 135091768,
+    (64, 64): 136959406, (64, 128): 139387922, (64, 256): 143330499, (64, 512): 135148597,
 }
 
 

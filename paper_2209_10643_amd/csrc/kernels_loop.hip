@@ -21,6 +21,7 @@
 namespace upir {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------ body functors
 struct BAxpy {
@@ -367,17 +368,19 @@ hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, con
 // 4l .. 4l+3 of every row of its strip (the within-tile unit assignment of
 // this body). A wavefront walks its strip top to bottom holding the rows
 // above and at the current one in registers, loads the rows below in groups
-// of JG (all in flight together), and gets its west/east neighbours from the
-// adjacent lanes (lane 0 and lane 63 load the tile's halo columns). Nothing
-// is staged in LDS, so no barrier separates loads from arithmetic.
+// of JG with the next group's loads issued before the current group's
+// arithmetic, and gets its west/east neighbours from the adjacent lanes
+// (lane 0 and lane 63 load the tile's halo columns). Nothing is staged in
+// LDS, so no barrier separates loads from arithmetic.
 constexpr int JT_W = 256;  // tile width (points)
-constexpr int JG = 8;      // rows loaded together per wavefront
+constexpr int JG = 4;      // rows per load group (two groups in flight per wavefront)
 
 // Residual reduction per lane. The float64 value of |u1 - u0| is only needed
 // where it can change the lane's maximum (or minimum): rounding to float32
 // is monotonic, so a point whose float32 |u1 - u0| is below the lane's
 // float32 maximum cannot hold the exact maximum. Only candidates at or above
-// it (a handful per lane) take the float64 path; the result is exact.
+// it take the float64 path, and a row of four points where none is a
+// candidate costs one comparison; the result is exact.
 template <int OP>
 struct ResidualAcc {
   float m32 = OP == RED_MIN ? __builtin_inff() : -1.0f;
@@ -398,48 +401,92 @@ struct ResidualAcc {
       }
     }
   }
+  // The four points of a lane's row; bit e of `mk` marks point e as in the
+  // loop box.
+  __device__ void add4(const f32x4 &v, const f32x4 &c, int mk) {
+    if (OP != RED_SUM) {
+      constexpr float NONE = OP == RED_MAX ? -1.0f : __builtin_inff();
+      const float d0 = mk & 1 ? fabsf(v.x - c.x) : NONE, d1 = mk & 2 ? fabsf(v.y - c.y) : NONE;
+      const float d2 = mk & 4 ? fabsf(v.z - c.z) : NONE, d3 = mk & 8 ? fabsf(v.w - c.w) : NONE;
+      const float dm = OP == RED_MAX ? fmaxf(fmaxf(d0, d1), fmaxf(d2, d3)) : fminf(fminf(d0, d1), fminf(d2, d3));
+      if (OP == RED_MAX ? dm < m32 : dm > m32) return;
+    }
+    if (mk & 1) add(v.x, c.x);
+    if (mk & 2) add(v.y, c.y);
+    if (mk & 4) add(v.z, c.z);
+    if (mk & 8) add(v.w, c.w);
+  }
 };
 
-// One row segment of a wavefront: the lane's four columns (c0 .. c0+3) and,
-// in `h`, lane 0's west halo (column c0-1) or lane 63's east halo (column
-// c0+4). EDGE loads only the columns [clo, chi] that in-box points read.
-template <bool EDGE>
-__device__ __forceinline__ void jacobi_load_row(const float *row, int64_t c0, int lane, int64_t clo, int64_t chi, f32x4 &v,
-                                       float &h) {
-  if (!EDGE || (c0 >= clo && c0 + 3 <= chi)) {
-    v = *(const f32x4 *)(row + c0);
-  } else {
-    float e[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) e[q] = (c0 + q >= clo && c0 + q <= chi) ? row[c0 + q] : 0.0f;
-    v = f32x4{e[0], e[1], e[2], e[3]};
-  }
-  const int64_t hc = lane == 0 ? c0 - 1 : c0 + 4;
-  h = 0.0f;
-  if ((lane == 0 || lane == WAVE - 1) && hc >= clo && hc <= chi) h = row[hc];
-}
-
-// Rows [ra, rb) of one wavefront's strip, columns of this lane. EDGE is the
-// path of tiles that cross the loop box's column bounds [jlo, jhi).
+// The rows of one wavefront's strip, rb - ra = n of them. Rows are read
+// through a buffer resource that starts 16 bytes before the tile's first
+// column in the row above the strip: lane l's four columns (tile columns
+// cl .. cl+3, cl = 4 l) sit at byte offset 16 (l + 1) of every row, the
+// halo columns at 12 (lane 0, tile column -1) and 1040 (lane 63, column
+// 256), and the row is the scalar offset. A lane that must not read an
+// address passes an offset past the resource's extent, which the hardware
+// answers with zero without touching memory, so the loads need no branches.
+// EDGE tiles cross the loop box's column bounds: they read only the tile
+// columns [clo, chi] that in-box points read and write only [wlo, whi); a
+// lane whose four columns straddle a read bound loads them one by one. Byte
+// offsets within a strip fit 32 bits (checked when the variant is chosen).
 template <bool EDGE, int RED, bool NT>
-__device__ __forceinline__ void jacobi_strip(const JacobiP &p, int64_t ra, int64_t rb, int64_t c0, int lane, int64_t clo,
-                                    int64_t chi, int64_t jlo, int64_t jhi, ResidualAcc<RED> &acc) {
-  const int64_t ld = p.ld;
-  f32x4 up, mid;
-  float hu, hm;
-  jacobi_load_row<EDGE>(p.src + (ra - 1) * ld, c0, lane, clo, chi, up, hu);
-  jacobi_load_row<EDGE>(p.src + ra * ld, c0, lane, clo, chi, mid, hm);
-  for (int64_t r = ra; r < rb; r += JG) {
-    f32x4 dn[JG];
-    float hd[JG];
+__device__ __forceinline__ void jacobi_strip(const float *sp, float *dp, int ld, int n, int lane, int clo, int chi,
+                                             int wlo, int whi, ResidualAcc<RED> &acc) {
+  constexpr uint32_t OFF = 0x80000000u;  // past the extent: reads as zero
+  const uint32_t rowb = 4u * (uint32_t)ld;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)(sp - 4), (short)0, (int)((uint32_t)(n + 1) * rowb + 1044u), 0x00020000);
+  const int cl = 4 * lane;
+  const bool in4 = !EDGE || (cl >= clo && cl + 3 <= chi);
+  const bool split = EDGE && !in4 && cl <= chi && cl + 3 >= clo;
+  const uint32_t vo = in4 ? 16u * (uint32_t)(lane + 1) : OFF;
+  const int hc = lane == 0 ? cl - 1 : cl + 4;
+  const uint32_t ho =
+      (lane == 0 || lane == WAVE - 1) && (!EDGE || (hc >= clo && hc <= chi)) ? 16u + 4u * (uint32_t)hc : OFF;
+  auto elem = [&](int x, int q) {
+    const uint32_t eo = cl + q >= clo && cl + q <= chi ? 16u + 4u * (uint32_t)(cl + q) : OFF;
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, eo, __builtin_amdgcn_readfirstlane(x * (int)rowb), 0));
+  };
+  auto row4 = [&](int x) {
+    f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, __builtin_amdgcn_readfirstlane(x * (int)rowb), 0));
+    if (EDGE && split) v = f32x4{elem(x, 0), elem(x, 1), elem(x, 2), elem(x, 3)};
+    return v;
+  };
+  auto halo = [&](int x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, ho, __builtin_amdgcn_readfirstlane(x * (int)rowb), 0));
+  };
+  // Points of this lane in the box (bit e: column cl + e) and, in EDGE tiles,
+  // the destination through a buffer resource: a lane writes its four
+  // columns with one store when all are in the box, else (in a wavefront
+  // that has such a lane) one by one, offsets past the extent dropping the
+  // columns outside the box.
+  int mk = 0xF;
+  if (EDGE) {
+    mk = 0;
 #pragma unroll
-    for (int q = 0; q < JG; ++q) {  // rows r+1 .. r+JG, clamped to rb (in the box's halo)
-      const int64_t rr = r + 1 + q < rb ? r + 1 + q : rb;
-      jacobi_load_row<EDGE>(p.src + rr * ld, c0, lane, clo, chi, dn[q], hd[q]);
-    }
+    for (int e = 0; e < 4; ++e) mk |= (cl + e >= wlo && cl + e < whi) ? 1 << e : 0;
+  }
+  const __amdgpu_buffer_rsrc_t rd =
+      __builtin_amdgcn_make_buffer_rsrc((void *)dp, (short)0, (int)((uint32_t)(n - 1) * rowb + 1024u), 0x00020000);
+  const uint32_t so4 = mk == 0xF ? 4u * (uint32_t)cl : OFF;
+  const bool part = EDGE && __builtin_amdgcn_ballot_w64(mk != 0xF && mk != 0) != 0;
+  f32x4 up = row4(0), mid = row4(1);
+  float hm = halo(1);
+  // Strip rows r+1 .. r+JG (clamped to n, the row below the strip).
+  auto load_group = [&](int r, f32x4 *dn, float *hd) {
 #pragma unroll
     for (int q = 0; q < JG; ++q) {
-      if (r + q >= rb) break;
+      const int x = (r + 1 + q < n ? r + 1 + q : n) + 1;
+      dn[q] = row4(x);
+      hd[q] = halo(x);
+    }
+  };
+  // Output rows r .. r+JG-1 of the strip from the rows held and a group below.
+  auto compute_group = [&](int r, const f32x4 *dn, const float *hd) {
+#pragma unroll
+    for (int q = 0; q < JG; ++q) {
+      if (r + q >= n) break;
       const float wsh = __shfl_up(mid.w, 1), esh = __shfl_down(mid.x, 1);
       const float Wm = lane == 0 ? hm : wsh, Ep = lane == WAVE - 1 ? hm : esh;
       const f32x4 S = dn[q];
@@ -448,30 +495,38 @@ __device__ __forceinline__ void jacobi_strip(const JacobiP &p, int64_t ra, int64
       v.y = ((up.y + S.y) + (mid.x + mid.z)) * 0.25f;
       v.z = ((up.z + S.z) + (mid.y + mid.w)) * 0.25f;
       v.w = ((up.w + S.w) + (mid.z + Ep)) * 0.25f;
-      float *out = p.dst + (r + q) * ld + c0;
-      if (!EDGE || (c0 >= jlo && c0 + 3 < jhi)) {
+      if (RED) acc.add4(v, mid, mk);
+      if (!EDGE) {
+        float *out = dp + __builtin_amdgcn_readfirstlane((r + q) * ld) + cl;
         if (NT) __builtin_nontemporal_store(v, (f32x4 *)out);
         else *(f32x4 *)out = v;
-        if (RED) {
-          acc.add(v.x, mid.x);
-          acc.add(v.y, mid.y);
-          acc.add(v.z, mid.z);
-          acc.add(v.w, mid.w);
-        }
       } else {
-        const float vv[4] = {v.x, v.y, v.z, v.w}, cc[4] = {mid.x, mid.y, mid.z, mid.w};
+        const int soff = __builtin_amdgcn_readfirstlane((r + q) * (int)rowb);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rd, so4, soff, 0);
+        if (part) {
+          const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (c0 + e >= jlo && c0 + e < jhi) {
-            out[e] = vv[e];
-            if (RED) acc.add(vv[e], cc[e]);
-          }
+          for (int e = 0; e < 4; ++e)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, vv[e]), rd,
+                                                  mk != 0xF && (mk >> e & 1) ? 4u * (uint32_t)(cl + e) : OFF, soff, 0);
         }
       }
       up = mid;
       mid = S;
       hm = hd[q];
     }
+  };
+  // Two groups in flight: the next group's loads are issued before the
+  // current group's arithmetic.
+  f32x4 A[JG], B[JG];
+  float hA[JG], hB[JG];
+  load_group(0, A, hA);
+  for (int r = 0; r < n; r += 2 * JG) {
+    if (r + JG < n) load_group(r + JG, B, hB);
+    compute_group(r, A, hA);
+    if (r + JG >= n) break;
+    if (r + 2 * JG < n) load_group(r + 2 * JG, A, hA);
+    compute_group(r + JG, B, hB);
   }
 }
 
@@ -480,11 +535,24 @@ __device__ __forceinline__ void jacobi_strip(const JacobiP &p, int64_t ra, int64
 // next sweep and is stored normally).
 template <int TH, int RED, bool NT>
 __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP p, RedK R) {
-  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, NW = blockDim.x / WAVE;
-  const int team = xcd_team(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x % WAVE;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), NW = blockDim.x / WAVE;
+  // An earlier loop's deferred fold rides on this kernel. Unless this loop
+  // combines its own reduction across workgroups now, the launch carries one
+  // extra workgroup, launched last, that only folds (its latency then hides
+  // behind the tiles still running); otherwise workgroup 0 folds after its
+  // tiles.
+  const bool xfold = has_fold_wg(R);
+  const int G = xfold ? gridDim.x - 1 : gridDim.x;
+  if (xfold && (int)blockIdx.x == G) {
+    run_fold(R.fold);
+    return;
+  }
+  const int team = xcd_team(blockIdx.x, G);
   const int SH = (TH + NW - 1) / NW;                          // strip height
   const int64_t ilo = L.lb[0], ihi = L.lb[0] + L.cnt[0];  // interior rows [ilo, ihi)
   const int64_t jlo = L.lb[1], jhi = L.lb[1] + L.cnt[1];
+  const int ld = (int)p.ld;
   ResidualAcc<RED> acc;
 
   auto do_tile = [&](int64_t m) {
@@ -493,13 +561,15 @@ __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP
     const int64_t s0 = i0 + (int64_t)w * SH, s1 = s0 + SH < i0 + TH ? s0 + SH : i0 + TH;
     const int64_t ra = s0 > ilo ? s0 : ilo, rb = s1 < ihi ? s1 : ihi;
     if (ra >= rb) return;
-    const int64_t c0 = j0 + 4 * lane;
+    const float *sp = p.src + (ra - 1) * p.ld + j0;
+    float *dp = p.dst + ra * p.ld + j0;
+    const int n = (int)(rb - ra);
     if (j0 >= jlo && j0 + JT_W <= jhi) {
-      jacobi_strip<false, RED, NT>(p, ra, rb, c0, lane, j0 - 1, j0 + JT_W, jlo, jhi, acc);
+      jacobi_strip<false, RED, NT>(sp, dp, ld, n, lane, -1, JT_W, 0, JT_W, acc);
     } else {
-      // columns read by in-box points of this tile (inclusive)
-      const int64_t clo = (j0 > jlo ? j0 : jlo) - 1, chi = (j0 + JT_W < jhi ? j0 + JT_W : jhi);
-      jacobi_strip<true, RED, NT>(p, ra, rb, c0, lane, clo, chi, jlo, jhi, acc);
+      // tile columns read by in-box points (inclusive) and written (half-open)
+      const int wlo = (int)((j0 > jlo ? j0 : jlo) - j0), whi = (int)((j0 + JT_W < jhi ? j0 + JT_W : jhi) - j0);
+      jacobi_strip<true, RED, NT>(sp, dp, ld, n, lane, wlo - 1, whi, wlo, whi, acc);
     }
   };
 
@@ -513,7 +583,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP
       for (int64_t m = m0; m < m0 + c && m < S.ntiles; ++m) do_tile(m);
   }
   if (RED) finish_reduction<double>(R, acc.m64);
-  fold_hook(R);
+  if (!xfold) fold_hook(R);
 }
 
 bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
@@ -526,12 +596,13 @@ bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
   if (S.policy != POL_STATIC && S.policy != POL_CHUNK) return false;
   if ((p.ld % 4) != 0 || ((uintptr_t)p.src % 16) != 0 || ((uintptr_t)p.dst % 16) != 0) return false;
   if (L.lb[1] < 1 || L.lb[0] < 1) return false;  // halo reads at lb-1 stay in the array
+  if ((int64_t)(th + 2) * p.ld * 4 + 2048 >= (1LL << 31)) return false;  // 32-bit byte offsets within a strip
   return true;
 }
 
 template <int TH, bool NT>
 static hipError_t go_jacobi_nt(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
-  const dim3 g(S.T), b(S.U);
+  const dim3 g(S.T + (has_fold_wg(R) ? 1 : 0)), b(S.U);
   switch (R.op) {
     case RED_NONE: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_NONE, NT>), g, b, 0, st, L, S, p, R); break;
     case RED_SUM: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_SUM, NT>), g, b, 0, st, L, S, p, R); break;
@@ -724,7 +795,7 @@ hipError_t launch_filter7_tile(const Filter7P &p, const LoopK &L, const SchedK &
 // The unit of a MATVEC loop is a wavefront: rows are owned by (team, wave)
 // under the schedule with U/64 units per team. Inside a row, lane l takes
 // columns 4l .. 4l+3 of every 256-column block in order, then the 64 lane
-// sums meet in a fixed butterfly.
+// sums meet in a fixed reduction tree.
 template <bool RED>
 __global__ void __launch_bounds__(1024) k_matvec(LoopK L, SchedK S, MatvecP p, RedK R) {
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;

@@ -939,7 +939,7 @@ upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for
   if (st) return st;
   // an async reduction outside the task graph defers its fold
   const bool defer = lp->has_red && lp->red.async && !for_task;
-  const int64_t nparts = (int64_t)pl.S.T * ((pl.S.U + 63) / 64);
+  const int64_t nparts = (int64_t)pl.S.T * ((pl.S.U + 63) / 64);  // one partial per wavefront
   if (defer) {
     st = ensure_fold_bufs(c, nparts);
     if (st) return st;

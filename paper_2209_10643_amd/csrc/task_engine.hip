@@ -147,7 +147,7 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
   const int tid = threadIdx.x, nt = blockDim.x;
   if (t.kind == UPIR_BODY_MATVEC) {
     // same arithmetic as the loop kernel's row: lane l takes columns
-    // 4l .. 4l+3 of each 256-column block in order, then a fixed butterfly
+    // 4l .. 4l+3 of each 256-column block in order, then a fixed tree
     const int lane = tid % WAVE, w = tid / WAVE, nw = nt / WAVE;
     auto row_dot = [&](int64_t r) {
       const float *a = t.A + r * t.lda;

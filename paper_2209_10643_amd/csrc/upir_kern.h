@@ -244,9 +244,49 @@ template <> __device__ inline long long red_identity<long long>(int op) {
   return op == RED_SUM ? 0LL : (op == RED_MAX ? (long long)0x8000000000000000ULL : 0x7FFFFFFFFFFFFFFFLL);
 }
 
-// Butterfly over the 64 lanes (fixed tree: xor 32, 16, ..., 1).
+// Lane v moved by one DPP step; lanes the row mask leaves out get `id`.
+template <int CTRL, int RM, class T>
+__device__ inline T dpp_move(T v, T id) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, id), __builtin_bit_cast(int, v), CTRL, RM, 0xF, false));
+  } else {
+    const unsigned long long vb = __builtin_bit_cast(unsigned long long, v), ib = __builtin_bit_cast(unsigned long long, id);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)ib, (int)(unsigned)vb, CTRL, RM, 0xF, false);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(ib >> 32), (int)(unsigned)(vb >> 32), CTRL, RM, 0xF, false);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
+template <class T>
+__device__ inline T read_lane63(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), WAVE - 1));
+  } else {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, WAVE - 1);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), WAVE - 1);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
+
+// Reduction over the 64 lanes, returned to every lane; a fixed tree, so the
+// result is deterministic. Workgroups of whole wavefronts (every lane
+// active) use DPP steps: pairs and quads, the two halves of each row of 16
+// lanes, then rows 0 + 1 and 2 + 3 and finally all four rows into lane 63.
+// Other workgroups use a butterfly over lane shuffles (xor 32, 16, ..., 1).
 template <class T>
 __device__ inline T wave_reduce(int op, T v) {
+  if (blockDim.x % WAVE == 0) {
+    const T id = red_identity<T>(op);
+    v = red_apply(op, v, dpp_move<0xB1, 0xF>(v, id));   // quad_perm [1,0,3,2]
+    v = red_apply(op, v, dpp_move<0x4E, 0xF>(v, id));   // quad_perm [2,3,0,1]
+    v = red_apply(op, v, dpp_move<0x141, 0xF>(v, id));  // row_half_mirror
+    v = red_apply(op, v, dpp_move<0x140, 0xF>(v, id));  // row_mirror
+    v = red_apply(op, v, dpp_move<0x142, 0xA>(v, id));  // row_bcast:15 into rows 1 and 3
+    v = red_apply(op, v, dpp_move<0x143, 0xC>(v, id));  // row_bcast:31 into rows 2 and 3
+    return read_lane63(v);
+  }
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) v = red_apply(op, v, __shfl_xor(v, s, WAVE));
   return v;
@@ -380,8 +420,8 @@ __device__ inline void combine_f64(const RedK &R, double wg, double *lds) { comb
 __device__ inline void combine_i64(const RedK &R, long long wg, long long *lds) { combine_slots<long long>(R, wg, lds); }
 
 // Deferred finish: one partial per wavefront, stored at
-// defer[workgroup * wavefronts-per-workgroup + wavefront]; no cross-workgroup
-// traffic in this kernel.
+// defer[workgroup * wavefronts-per-workgroup + wavefront]; no barrier and no
+// cross-workgroup traffic in this kernel.
 template <class T>
 __device__ inline void defer_partial(const RedK &R, T lane) {
   const T w = wave_reduce(R.op, lane);
@@ -423,23 +463,46 @@ __device__ inline void finish_reduction<long long>(const RedK &R, long long lane
 
 // Fold of a deferred reduction by one whole workgroup: thread t takes
 // partials t, t + U, ... in order, then a fixed tree; `init` is applied
-// once. The partials were written by an earlier kernel on the same stream,
-// so plain loads see them.
+// once. A thread's partials are loaded FB at a time, all in flight
+// together. The partials were written by an earlier kernel on the same
+// stream, so plain loads see them.
+template <class V>
+__device__ inline V fold_value(unsigned long long b) {
+  if constexpr (std::is_same<V, long long>::value) return (long long)b;
+  else return __builtin_bit_cast(double, b);
+}
+
+template <class V>
+__device__ inline void fold_typed(const FoldK &F, V *lds) {
+  constexpr int FB = 8;
+  const long long U = blockDim.x;
+  V v = red_identity<V>(F.op);
+  unsigned long long b[FB];
+  for (long long i0 = threadIdx.x; i0 < F.count; i0 += FB * U) {
+#pragma unroll
+    for (int q = 0; q < FB; ++q) b[q] = i0 + q * U < F.count ? F.part[i0 + q * U] : 0ULL;
+#pragma unroll
+    for (int q = 0; q < FB; ++q)
+      if (i0 + q * U < F.count) v = red_apply(F.op, v, fold_value<V>(b[q]));
+  }
+  v = block_reduce(F.op, v, lds);
+  if (threadIdx.x == 0) {
+    if constexpr (std::is_same<V, long long>::value) *(long long *)F.result = red_apply(F.op, F.init_i, v);
+    else *(double *)F.result = red_apply(F.op, F.init, v);
+  }
+}
+
 __device__ inline void run_fold(const FoldK &F) {
   __shared__ double fd[16];
   __shared__ long long fi[16];
-  if (F.is_int) {
-    long long v = red_identity<long long>(F.op);
-    for (long long i = threadIdx.x; i < F.count; i += blockDim.x) v = red_apply(F.op, v, (long long)F.part[i]);
-    v = block_reduce(F.op, v, fi);
-    if (threadIdx.x == 0) *(long long *)F.result = red_apply(F.op, F.init_i, v);
-  } else {
-    double v = red_identity<double>(F.op);
-    for (long long i = threadIdx.x; i < F.count; i += blockDim.x)
-      v = red_apply(F.op, v, __builtin_bit_cast(double, F.part[i]));
-    v = block_reduce(F.op, v, fd);
-    if (threadIdx.x == 0) *(double *)F.result = red_apply(F.op, F.init, v);
-  }
+  if (F.is_int) fold_typed<long long>(F, fi);
+  else fold_typed<double>(F, fd);
+}
+
+// A kernel that carries an earlier loop's fold may give it a workgroup of
+// its own when no cross-workgroup combine of its own reduction runs in it.
+__host__ __device__ inline bool has_fold_wg(const RedK &R) {
+  return R.fold.count > 0 && (R.op == RED_NONE || R.defer != nullptr);
 }
 
 // Called by every thread at the very end of a loop kernel: workgroup 0 runs
