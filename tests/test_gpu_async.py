@@ -220,3 +220,34 @@ def test_tuning_an_async_loop_leaves_its_result_alone(ctx):
     want_u, want_r = bodies.jacobi5(u0, 1)
     assert np.array_equal(b.cpu().numpy(), want_u) and res.item() == want_r[0]
     ctx.free(hs[0])
+
+
+@pytest.mark.parametrize("jacobi_red", ["sync", "none", "async"])
+def test_fold_rides_on_a_jacobi_sweep(ctx, jacobi_red):
+    """An async loop's fold carried by the next kernel, a Jacobi sweep: by an
+    extra workgroup when the sweep combines nothing across workgroups itself
+    (no reduction, or an async one), else by workgroup 0 after its tiles."""
+    note(f"fold on jacobi ({jacobi_red})")
+    v = synth.uniform_pm1(21, 0, 70001)
+    t = dev(v)
+    r1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    first = ctx.loop(U.UPIR_BODY_SUM, U.upir_sum_args(t.data_ptr(), U.UPIR_DT_F32, 0), [(0, len(v), 1)], None,
+                     H.make_red(U.UPIR_RED_MAX, r1.data_ptr(), async_=True))
+    u0 = grid(260, 1028, seed=22)
+    a, b = dev(u0), dev(u0)
+    r2 = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    red = None if jacobi_red == "none" else H.make_red(U.UPIR_RED_MAX, r2.data_ptr(), async_=(jacobi_red == "async"))
+    sweep = ctx.loop(U.UPIR_BODY_JACOBI5, U.upir_jacobi5_args(a.data_ptr(), b.data_ptr(), u0.shape[1]),
+                     [(1, u0.shape[0] - 1, 1), (1, u0.shape[1] - 1, 1)], None, red)
+    assert U.VARIANTS[ctx.resolve(sweep)[2]] == "jacobi_tile"
+    for rep in range(2):
+        r1.zero_()
+        r2.fill_(-1.0)
+        ctx.launch([first, sweep])
+        ctx.sync()
+        assert r1.item() == float(v.max()), rep
+        want_u, want_r = bodies.jacobi5(u0, 1)
+        assert np.array_equal(b.cpu().numpy(), want_u), rep
+        assert r2.item() == (-1.0 if jacobi_red == "none" else want_r[0]), rep
+    ctx.free(first)
+    ctx.free(sweep)

@@ -347,6 +347,46 @@ def test_jacobi_tile_strips_and_ops(ctx, th, units, op):
         assert np.array_equal(got_r, want_r)
 
 
+@pytest.mark.parametrize("box,th,units,op", [
+    (((5, 203), (3, 517)), 16, 256, "max"),    # box edges inside lanes on both sides
+    (((1, 209), (2, 518)), 64, 512, "min"),
+    (((7, 150), (1, 513)), 8, 64, "sum"),      # left edge on a lane boundary, right edge inside a lane
+    (((2, 3), (255, 258)), 4, 128, "max"),     # one row across a tile boundary
+])
+def test_jacobi_tile_sub_box(ctx, box, th, units, op):
+    """A loop box strictly inside the grid: only box points are written (the
+    rest of the destination keeps its sentinel), lanes whose four columns
+    straddle a box edge load and store column by column, and the residual
+    covers the box alone."""
+    (i0, i1), (j0, j1) = box
+    note(f"jacobi sub-box {box} tile ({th}, 256) units {units} op {op}")
+    u0 = jacobi_grid(210, 532, seed=31 + th)
+    src = dev(u0)
+    dst = torch.full(u0.shape, -7.0, device="cuda")
+    res = torch.zeros(1, dtype=torch.float64, device="cuda")
+    op_ = OPS[op]
+    red = H.make_red(op_, res.data_ptr(), init=float("inf") if op_ == U.UPIR_RED_MIN else 0.0)
+    lp = ctx.loop(U.UPIR_BODY_JACOBI5, U.upir_jacobi5_args(src.data_ptr(), dst.data_ptr(), u0.shape[1]),
+                  [(i0, i1, 1), (j0, j1, 1)], H.make_sched(U.UPIR_SCHED_STATIC, tile=(th, 256)), red)
+    sp = H.make_spmd(0, units)
+    assert U.VARIANTS[ctx.resolve(lp, sp)[2]] == "jacobi_tile"
+    ctx.launch(lp, sp)
+    ctx.sync()
+    ctx.free(lp)
+    full = bodies.jacobi5_sweep_f32(u0)
+    want = np.full(u0.shape, -7.0, np.float32)
+    want[i0:i1, j0:j1] = full[i0:i1, j0:j1]
+    assert np.array_equal(dst.cpu().numpy(), want)
+    # the oracle's residual over the interior of the box grown by its halo
+    want_r = bodies.update_f64(full[i0 - 1:i1 + 1, j0 - 1:j1 + 1], u0[i0 - 1:i1 + 1, j0 - 1:j1 + 1], op)
+    got_r = res.item()
+    if op == "sum":
+        n = (i1 - i0) * (j1 - j0)
+        assert abs(got_r - want_r) <= n * 2.0 ** -53 * want_r
+    else:
+        assert got_r == want_r
+
+
 def test_jacobi_linear_field_is_fixed(ctx):
     N = 300
     i, j = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
