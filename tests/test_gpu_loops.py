@@ -584,6 +584,34 @@ def test_jacobi_full_size_benchmark_configuration(ctx):
         ctx.free(h)
 
 
+def test_jacobi_beyond_last_level_cache(ctx):
+    """Two grids larger than the 256 MB cache (2 x 151 MB): the sweep stores
+    with the non-temporal hint. Three sweeps with async max residuals, grid
+    and residuals bit-exact against the oracle."""
+    Hh, W, sweeps = 8192, 4612, 3
+    note(f"jacobi {Hh}x{W} beyond the cache")
+    u0 = jacobi_grid(Hh, W, seed=41)
+    a, b = dev(u0), dev(u0)
+    res = torch.zeros(sweeps, dtype=torch.float64, device="cuda")
+    hs = []
+    for k in range(sweeps):
+        src, dst = (a, b) if k % 2 == 0 else (b, a)
+        hs.append(ctx.loop(U.UPIR_BODY_JACOBI5, U.upir_jacobi5_args(src.data_ptr(), dst.data_ptr(), W),
+                           [(1, Hh - 1, 1), (1, W - 1, 1)], None,
+                           H.make_red(U.UPIR_RED_MAX, res[k:].data_ptr(), async_=True)))
+    assert U.VARIANTS[ctx.resolve(hs[0])[2]] == "jacobi_tile"
+    assert 2 * Hh * W * 4 > 256 << 20
+    ctx.launch(hs)
+    ctx.sync()
+    want_u, want_r = bodies.jacobi5(u0, sweeps)
+    assert np.array_equal(b.cpu().numpy(), want_u)
+    assert np.array_equal(res.cpu().numpy(), want_r)
+    for h in hs:
+        ctx.free(h)
+    del a, b
+    torch.cuda.empty_cache()
+
+
 def test_axpy_beyond_int32_indices(ctx):
     """n = 2^31 + 17 (16 GiB of operands): 64-bit iteration indices through
     the non-temporal streaming kernel. Outputs at 2,000 sampled indices and
