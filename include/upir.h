@@ -171,7 +171,7 @@ typedef struct {
                                 sync): the kernel leaves one partial per
                                 wavefront and the cross-workgroup fold is
                                 deferred to the next loop kernel on the
-                                context (its workgroup 0) or to the next
+                                context (one of its workgroups) or to the next
                                 upir_reduce_wait / upir_sync / graph end /
                                 taskwait / data_update / unmap (wait-release).
                                 A device result is valid after that point, a

@@ -65,7 +65,7 @@ struct RedK {
   unsigned long long *slots;  // two words per workgroup: value, flag
   long long spin_limit;       // bound on the combiner's wait per slot
   unsigned long long *defer;  // non-null: leave one partial per wavefront here, fold later
-  FoldK fold;                 // an earlier loop's deferred fold, run by workgroup 0
+  FoldK fold;                 // an earlier loop's deferred fold, run by one workgroup
 };
 
 // Empty float slot: all ones, a NaN that neither arithmetic nor a float32 to

@@ -2,9 +2,9 @@
 the loop kernel, wait-release at the next synchronisation point (sec. 5).
 
 A loop whose reduction has ``async = 1`` leaves one partial per wavefront;
-the fold runs on workgroup 0 of the next loop kernel on the context's stream,
-or as a one-workgroup kernel at upir_sync / upir_reduce_wait / graph end /
-taskwait. Results must equal the synchronous path's: exact for max, min and
+the fold runs in the next loop kernel on the context's stream (workgroup 0,
+or an extra workgroup of a Jacobi sweep), or as a one-workgroup kernel at
+upir_sync / upir_reduce_wait / graph end / taskwait. Results must equal the synchronous path's: exact for max, min and
 integer sums, within the float sum bound otherwise.
 """
 import ctypes as C
