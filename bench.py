@@ -66,10 +66,11 @@ class Timer:
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB copy), bytes,
 # from profiles/jacobi5_4096_hbm_traffic.md. Valid for the kernel as profiled.
 JACOBI_4096_TRAFFIC = {
-    (8, 64): 135425454, (8, 128): 135207870, (8, 256): 135284897, (8, 512): 135737564,
-    (16, 64): 143530218, (16, 128): 135341068, (16, 256): 135049807, (16, 512): 135252386,
-    (32, 64): 139607244, (32, 128): 143496751, (32, 256): 135212857, (32, 512): 135091768,
-    (64, 64): 136959406, (64, 128): 139387922, (64, 256): 143330499, (64, 512): 135148597,
+    (8, 64): 135416886, (8, 128): 135224800, (8, 256): 135283609, (8, 512): 135725119,
+    (16, 64): 143506762, (16, 128): 135294624, (16, 256): 135083440, (16, 512): 135266244,
+    (32, 64): 139472145, (32, 128): 143320625, (32, 256): 135185830, (32, 512): 135079878,
+    (64, 64): 136985449, (64, 128): 139434054, (64, 256): 143244480, (64, 512): 135158258,
+    (128, 64): 136217166, (128, 128): 137087964, (128, 256): 139486804, (128, 512): 143366267,
 }
 
 

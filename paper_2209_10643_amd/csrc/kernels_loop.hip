@@ -591,7 +591,7 @@ bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
   if (L.step[0] != 1 || L.step[1] != 1) return false;
   if (S.tile[1] != JT_W) return false;
   const int th = S.tile[0];
-  if (th != 4 && th != 8 && th != 16 && th != 32 && th != 64) return false;
+  if (th != 4 && th != 8 && th != 16 && th != 32 && th != 64 && th != 128) return false;
   if (S.U % WAVE != 0 || S.U < WAVE) return false;
   if (S.policy != POL_STATIC && S.policy != POL_CHUNK) return false;
   if ((p.ld % 4) != 0 || ((uintptr_t)p.src % 16) != 0 || ((uintptr_t)p.dst % 16) != 0) return false;
@@ -626,6 +626,7 @@ hipError_t launch_jacobi_tile(const JacobiP &p, const LoopK &L, const SchedK &S,
     case 16: return go_jacobi<16>(p, L, S, R, st);
     case 32: return go_jacobi<32>(p, L, S, R, st);
     case 64: return go_jacobi<64>(p, L, S, R, st);
+    case 128: return go_jacobi<128>(p, L, S, R, st);
   }
   return hipErrorInvalidValue;
 }

@@ -610,9 +610,9 @@ static std::vector<Cand> candidates(upir_ctx *c, const upir_loop_obj *lp) {
       break;
     case UPIR_BODY_JACOBI5:
     case UPIR_BODY_FILTER7:
-      for (int th : {8, 16, 32, 64})
+      for (int th : {8, 16, 32, 64, 128})
         for (int32_t U : {64, 128, 256, 512})
-          if (U <= th * 64) add(0, U, UPIR_SCHED_STATIC, 0, th, 256);
+          if (U <= th * 64 && (th < 128 || lp->kind == UPIR_BODY_JACOBI5)) add(0, U, UPIR_SCHED_STATIC, 0, th, 256);
       break;
     case UPIR_BODY_MATVEC:
       for (int32_t U : {64, 256, 1024})

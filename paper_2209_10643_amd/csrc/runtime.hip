@@ -671,12 +671,14 @@ void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sc
     case UPIR_BODY_FILTER7: {
       // the tallest tile (longest wavefront strips) that still gives every
       // SIMD four wavefronts: at least 4 x CUs tiles of 4 wavefronts each
+      // (128-row tiles: Jacobi only)
       sc.policy = UPIR_SCHED_STATIC;
       sc.tile[1] = 256;
       sc.tile[0] = 4;
       const int64_t ct = cdiv(std::max<int64_t>(lp->cnt[1], 1), 256);
-      for (int th : {64, 32, 16, 8})
-        if (cdiv(std::max<int64_t>(lp->cnt[0], 1), th) * ct >= 4LL * c->num_cus) {
+      for (int th : {128, 64, 32, 16, 8})
+        if ((th < 128 || lp->kind == UPIR_BODY_JACOBI5) &&
+            cdiv(std::max<int64_t>(lp->cnt[0], 1), th) * ct >= 4LL * c->num_cus) {
           sc.tile[0] = th;
           break;
         }

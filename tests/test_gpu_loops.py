@@ -326,7 +326,7 @@ OPS = {"max": U.UPIR_RED_MAX, "min": U.UPIR_RED_MIN, "sum": U.UPIR_RED_SUM}
 
 @pytest.mark.parametrize("th,units,op", [
     (4, 64, "max"), (16, 192, "max"), (64, 64, "max"), (64, 512, "min"), (8, 256, "sum"), (32, 128, "sum"),
-    (32, 256, "min"),
+    (32, 256, "min"), (128, 256, "max"), (128, 1024, "sum"),
 ])
 def test_jacobi_tile_strips_and_ops(ctx, th, units, op):
     """Tile heights, wavefront counts (192: strips of unequal length) and the
