@@ -537,15 +537,16 @@ template <int TH, int RED, bool NT>
 __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP p, RedK R) {
   const int lane = threadIdx.x % WAVE;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), NW = blockDim.x / WAVE;
-  // An earlier loop's deferred fold rides on this kernel. Unless this loop
-  // combines its own reduction across workgroups now, the launch carries one
-  // extra workgroup, launched last, that only folds (its latency then hides
-  // behind the tiles still running); otherwise workgroup 0 folds after its
-  // tiles.
-  const bool xfold = has_fold_wg(R);
-  const int G = xfold ? gridDim.x - 1 : gridDim.x;
-  if (xfold && (int)blockIdx.x == G) {
-    run_fold(R.fold);
+  // The launch's cross-workgroup work goes to one extra workgroup, launched
+  // last and given no tile, so that its latency hides behind the tiles still
+  // running: the fold of an earlier loop's deferred reduction, and the
+  // combine of this loop's own synchronous reduction (as the last-launched
+  // workgroup it is the combiner; its own value is the identity).
+  const bool xwg = jacobi_extra_wg(R);
+  const int G = xwg ? gridDim.x - 1 : gridDim.x;
+  if (xwg && (int)blockIdx.x == G) {
+    if (R.fold.count > 0) run_fold(R.fold);
+    if (RED && !R.defer) finish_reduction<double>(R, ResidualAcc<RED>().m64);
     return;
   }
   const int team = xcd_team(blockIdx.x, G);
@@ -583,7 +584,6 @@ __global__ void __launch_bounds__(1024) k_jacobi_tile(LoopK L, SchedK S, JacobiP
       for (int64_t m = m0; m < m0 + c && m < S.ntiles; ++m) do_tile(m);
   }
   if (RED) finish_reduction<double>(R, acc.m64);
-  if (!xfold) fold_hook(R);
 }
 
 bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
@@ -602,7 +602,7 @@ bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S) {
 
 template <int TH, bool NT>
 static hipError_t go_jacobi_nt(const JacobiP &p, const LoopK &L, const SchedK &S, const RedK &R, hipStream_t st) {
-  const dim3 g(S.T + (has_fold_wg(R) ? 1 : 0)), b(S.U);
+  const dim3 g(S.T + (jacobi_extra_wg(R) ? 1 : 0)), b(S.U);
   switch (R.op) {
     case RED_NONE: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_NONE, NT>), g, b, 0, st, L, S, p, R); break;
     case RED_SUM: hipLaunchKernelGGL((k_jacobi_tile<TH, RED_SUM, NT>), g, b, 0, st, L, S, p, R); break;

@@ -499,10 +499,10 @@ __device__ inline void run_fold(const FoldK &F) {
   else fold_typed<double>(F, fd);
 }
 
-// A kernel that carries an earlier loop's fold may give it a workgroup of
-// its own when no cross-workgroup combine of its own reduction runs in it.
-__host__ __device__ inline bool has_fold_wg(const RedK &R) {
-  return R.fold.count > 0 && (R.op == RED_NONE || R.defer != nullptr);
+// The tiled Jacobi kernel launches one extra workgroup for its
+// cross-workgroup work: an earlier loop's fold, its own synchronous combine.
+__host__ __device__ inline bool jacobi_extra_wg(const RedK &R) {
+  return R.fold.count > 0 || (R.op != RED_NONE && R.defer == nullptr);
 }
 
 // Called by every thread at the very end of a loop kernel: workgroup 0 runs
