@@ -66,11 +66,11 @@ class Timer:
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB copy), bytes,
 # from profiles/jacobi5_4096_hbm_traffic.md. Valid for the kernel as profiled.
 JACOBI_4096_TRAFFIC = {
-    (8, 64): 135416886, (8, 128): 135224800, (8, 256): 135283609, (8, 512): 135725119,
-    (16, 64): 143506762, (16, 128): 135294624, (16, 256): 135083440, (16, 512): 135266244,
-    (32, 64): 139472145, (32, 128): 143320625, (32, 256): 135185830, (32, 512): 135079878,
-    (64, 64): 136985449, (64, 128): 139434054, (64, 256): 143244480, (64, 512): 135158258,
-    (128, 64): 136217166, (128, 128): 137087964, (128, 256): 139486804, (128, 512): 143366267,
+    (8, 64): 135433350, (8, 128): 135174668, (8, 256): 135249589, (8, 512): 135709125,
+    (16, 64): 143487776, (16, 128): 135212056, (16, 256): 135029772, (16, 512): 135248074,
+    (32, 64): 139523536, (32, 128): 143261895, (32, 256): 135118046, (32, 512): 135032892,
+    (64, 64): 137089719, (64, 128): 139507509, (64, 256): 143303285, (64, 512): 135211432,
+    (128, 64): 136205321, (128, 128): 137052423, (128, 256): 139448022, (128, 512): 143348225,
 }
 
 
