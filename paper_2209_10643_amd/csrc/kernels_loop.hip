@@ -373,7 +373,6 @@ hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, con
 // (lane 0 and lane 63 load the tile's halo columns). Nothing is staged in
 // LDS, so no barrier separates loads from arithmetic.
 constexpr int JT_W = 256;  // tile width (points)
-constexpr int JG = 4;      // rows per load group (two groups in flight per wavefront)
 
 // Residual reduction per lane. The float64 value of |u1 - u0| is only needed
 // where it can change the lane's maximum (or minimum): rounding to float32
@@ -434,6 +433,9 @@ template <bool EDGE, int RED, bool NT>
 __device__ __forceinline__ void jacobi_strip(const float *sp, float *dp, int ld, int n, int lane, int clo, int chi,
                                              int wlo, int whi, ResidualAcc<RED> &acc) {
   constexpr uint32_t OFF = 0x80000000u;  // past the extent: reads as zero
+  // rows per load group: 4 without a residual, 2 with one (the residual's
+  // registers and arithmetic leave room for fewer rows in flight)
+  constexpr int JG = RED != RED_NONE ? 2 : 4;
   const uint32_t rowb = 4u * (uint32_t)ld;
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void *)(sp - 4), (short)0, (int)((uint32_t)(n + 1) * rowb + 1044u), 0x00020000);
