@@ -66,11 +66,11 @@ class Timer:
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB copy), bytes,
 # from profiles/jacobi5_4096_hbm_traffic.md. Valid for the kernel as profiled.
 JACOBI_4096_TRAFFIC = {
-    (8, 64): 135433350, (8, 128): 135174668, (8, 256): 135249589, (8, 512): 135709125,
-    (16, 64): 143487776, (16, 128): 135212056, (16, 256): 135029772, (16, 512): 135248074,
-    (32, 64): 139523536, (32, 128): 143261895, (32, 256): 135118046, (32, 512): 135032892,
-    (64, 64): 137089719, (64, 128): 139507509, (64, 256): 143303285, (64, 512): 135211432,
-    (128, 64): 136205321, (128, 128): 137052423, (128, 256): 139448022, (128, 512): 143348225,
+    (8, 64): 142904433, (8, 128): 135163693, (8, 256): 135231792, (8, 512): 135703210,
+    (16, 64): 143522926, (16, 128): 142072313, (16, 256): 135023410, (16, 512): 135219782,
+    (32, 64): 139220740, (32, 128): 143329295, (32, 256): 142956880, (32, 512): 135002904,
+    (64, 64): 136930246, (64, 128): 139340149, (64, 256): 143342950, (64, 512): 140122076,
+    (128, 64): 136003482, (128, 128): 136952144, (128, 256): 139171625, (128, 512): 143239116,
 }
 
 
