@@ -199,7 +199,16 @@ def bench_axpy(torch, ctx, timer, reps=1000):
     out = {"n": n, "us_per_loop": round(per * 1e3, 3), "GBps": round(12 * n / (per * 1e-3) / 1e9, 1),
            "variant": U.VARIANTS[v], "teams": sp.num_teams, "units": sp.num_units,
            "note": "12 MiB working set: cache resident (L2 / MALL), 1000 back-to-back loops in one graph"}
-    # large n (working set > 256 MB MALL)
+    out.update(bench_stream_large(torch, ctx, timer))
+    ctx.graph_destroy(g)
+    ctx.free(lp)
+    out["sweep"] = axpy_sum_sweep(torch, ctx)
+    return out
+
+
+def bench_stream_large(torch, ctx, timer, reps=10):
+    """AXPY + sum and SUM alone at n = 2^28 (working sets of 3 GiB and 1 GiB,
+    beyond the 256 MB MALL): eager launches between HIP events."""
     nb = 1 << 28
     xb = synth.uniform_pm1_torch(1, 0, nb, device="cuda")
     yb = synth.uniform_pm1_torch(1, 1, nb, device="cuda")
@@ -207,21 +216,18 @@ def bench_axpy(torch, ctx, timer, reps=1000):
     lb = ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, xb.data_ptr(), yb.data_ptr()), [(0, nb, 1)], None,
                   H.make_red(U.UPIR_RED_SUM, rb.data_ptr()))
     ctx.launch(lb)
-    msb = timer.time(lambda: ctx.launch(lb), 10)
-    out["large_n"] = nb
-    out["large_GBps"] = round(12 * nb / (msb * 1e-3) / 1e9, 1)
+    msb = timer.time(lambda: ctx.launch(lb), reps)
     sb = torch.zeros(1, dtype=torch.float64, device="cuda")
     ls = ctx.loop(U.UPIR_BODY_SUM, U.upir_sum_args(xb.data_ptr(), U.UPIR_DT_F32, 0), [(0, nb, 1)], None,
                   H.make_red(U.UPIR_RED_SUM, sb.data_ptr()))
     ctx.launch(ls)
-    mss = timer.time(lambda: ctx.launch(ls), 10)
-    out["large_sum_GBps"] = round(4 * nb / (mss * 1e-3) / 1e9, 1)
-    ctx.graph_destroy(g)
-    for h in (lp, lb, ls):
+    mss = timer.time(lambda: ctx.launch(ls), reps)
+    for h in (lb, ls):
         ctx.free(h)
     del xb, yb
-    out["sweep"] = axpy_sum_sweep(torch, ctx)
-    return out
+    torch.cuda.empty_cache()
+    return {"large_n": nb, "large_GBps": round(12 * nb / (msb * 1e-3) / 1e9, 1),
+            "large_sum_GBps": round(4 * nb / (mss * 1e-3) / 1e9, 1)}
 
 
 def axpy_sum_sweep(torch, ctx, reps=10):
@@ -738,7 +744,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--configs", default="1,1L,0,2,3,4,P,D",
                     help="1 Jacobi 4096^2 (always timed: the headline), 1L Jacobi 16384^2, 0 AXPY+sum, "
-                         "2 matmul, 3 batched tasks, 4 learned schedule, P the paper's size grids, "
+                         "0L AXPY+sum and SUM at 2^28 only, 2 matmul, 3 batched tasks, 4 learned schedule, P the paper's size grids, "
                          "D overlapped data movement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -812,6 +818,9 @@ def main():
     if "0" in configs:
         log("axpy")
         extras["axpy_sum"] = bench_axpy(torch, ctx, timer)
+    elif "0L" in configs:
+        log("axpy + sum and sum at 2^28")
+        extras["axpy_sum"] = bench_stream_large(torch, ctx, timer, reps=3)
     if "2" in configs:
         log("matmul")
         extras["matmul_4096"] = bench_matmul(torch, ctx, timer)
