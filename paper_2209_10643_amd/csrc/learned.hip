@@ -775,16 +775,20 @@ static upir_status time_candidate(upir_ctx *c, upir_loop_obj *tmp, const Cand &k
   HIPTRY(c, hipEventCreate(&a));
   HIPTRY(c, hipEventCreate(&b));
   for (int r = 0; r < reps && st == UPIR_OK; ++r) {
-    hipEventRecord(a, c->stream);
+    if (hipEventRecord(a, c->stream) != hipSuccess) {
+      st = upir_fail(c, UPIR_EHIP, "event record");
+      break;
+    }
     st = launch_plan(c, tmp, pl, false);
-    hipEventRecord(b, c->stream);
-    if (hipEventSynchronize(b) != hipSuccess) st = upir_fail(c, UPIR_EHIP, "event wait");
+    if (st) break;
     float t = 0;
-    hipEventElapsedTime(&t, a, b);
+    if (hipEventRecord(b, c->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&t, a, b) != hipSuccess)
+      st = upir_fail(c, UPIR_EHIP, "event wait");
     ms.push_back(t);
   }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   if (st) return st;
   std::sort(ms.begin(), ms.end());
   us = 1e3 * ms[ms.size() / 2];

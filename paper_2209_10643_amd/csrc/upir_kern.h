@@ -304,7 +304,7 @@ __device__ inline T block_reduce(int op, T v, T *lds) {
   __syncthreads();
   T r = red_identity<T>(op);
   if (threadIdx.x < WAVE) {
-    r = threadIdx.x < nw ? lds[threadIdx.x] : red_identity<T>(op);
+    r = (int)threadIdx.x < nw ? lds[threadIdx.x] : red_identity<T>(op);
     r = wave_reduce(op, r);
   }
   return r;
