@@ -15,7 +15,10 @@ Readings (the paper is silent or inconsistent):
 * Reductions over float32 data are returned in float64.
 * Stencil: Jacobi 5-point update ``((N + S) + (W + E)) * 0.25`` on the
   interior, boundary fixed, with the sweep's update max-norm as residual.
-* Matmul: row-major C = A B, k ascending, every product exact in float64.
+* Matmul: row-major C = A B in float64. Every product of two float32
+  values is exact in float64; the float64 sums come from a library matrix
+  product (its own summation order, rounding error far below every
+  tolerance used); ``matmul_entry`` gives one entry correctly rounded.
 * BF16 splitting (an extension beyond the paper): ``hi = rne_bf16(a)``,
   ``lo = rne_bf16(a - hi)``.
 """

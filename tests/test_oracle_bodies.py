@@ -254,6 +254,68 @@ def test_matmul_identity_and_entry():
         assert abs(C[i, j] - float(exact)) <= 1e-12 * max(1.0, abs(float(exact)))
 
 
+def _bf16_round_fraction(x) -> F:
+    """Nearest bfloat16 (8 significant bits, ties to even) of a finite,
+    normal-range value, computed on exact rationals: scale by the bfloat16
+    ulp of x's binade and round the quotient to the nearest integer."""
+    fx = F(float(x))
+    if fx == 0:
+        return F(0)
+    e = math.floor(math.log2(abs(float(fx))))
+    ulp = F(2) ** (e - 7)
+    q = fx / ulp
+    fl = q.numerator // q.denominator
+    rem = q - fl
+    if rem > F(1, 2) or (rem == F(1, 2) and fl % 2 == 1):
+        fl += 1
+    return fl * ulp
+
+
+def test_matmul_bf16_and_split3_closed_form_one_by_one():
+    # a = 1 + 2^-9: its bfloat16 rounding is 1 (2^-9 is below half an ulp of
+    # 1, which is 2^-7) and the residual 2^-9 is a bfloat16 number, so the
+    # one-pass product of the roundings is exactly 1 and the three-pass split
+    # product lo*hi + hi*lo + hi*hi is exactly 1 + 2^-8 (the true product is
+    # 1 + 2^-8 + 2^-18: the split drops only lo*lo).
+    a = np.array([[1 + 2 ** -9]], np.float32)
+    assert bodies.matmul_bf16(a, a)[0, 0] == 1.0
+    assert bodies.matmul_split3(a, a)[0, 0] == 1 + 2 ** -8
+    assert bodies.matmul(a, a)[0, 0] == (1 + 2 ** -9) ** 2
+
+
+def test_matmul_bf16_and_split3_exact_rationals():
+    # non-integer 2 x 3 and 3 x 2 operands whose entries all have distinct
+    # high and low bfloat16 parts; both compositions checked entry by entry
+    # against exact rational arithmetic on an independent rounding
+    A = np.array([[1.2345678, -0.3141593, 7.0001],
+                  [2.5e-3, -19.75003, 0.6666667]], np.float32)
+    B = np.array([[0.1, -2.7182817],
+                  [1.4142135, 33.333336],
+                  [-0.0078125001, 5.55555]], np.float32)
+    hiA = [[_bf16_round_fraction(v) for v in r] for r in A]
+    hiB = [[_bf16_round_fraction(v) for v in r] for r in B]
+    loA = [[_bf16_round_fraction(float(F(float(v)) - h)) for v, h in zip(r, hr)] for r, hr in zip(A, hiA)]
+    loB = [[_bf16_round_fraction(float(F(float(v)) - h)) for v, h in zip(r, hr)] for r, hr in zip(B, hiB)]
+    for r in range(2):
+        for c in range(3):
+            assert loA[r][c] != 0 and hiA[r][c] != F(float(A[r, c]))
+    Cb = bodies.matmul_bf16(A, B)
+    Cs = bodies.matmul_split3(A, B)
+    for i in range(2):
+        for j in range(2):
+            one = sum((hiA[i][k] * hiB[k][j] for k in range(3)), F(0))
+            three = sum((loA[i][k] * hiB[k][j] + hiA[i][k] * loB[k][j] + hiA[i][k] * hiB[k][j]
+                         for k in range(3)), F(0))
+            # three float64 products of bfloat16 values are exact; the sums
+            # round at most once per addition
+            assert abs(F(float(Cb[i, j])) - one) <= abs(one) * F(2) ** -50
+            assert abs(F(float(Cs[i, j])) - three) <= abs(three) * F(2) ** -49
+            # and they differ from each other and from the unrounded product
+            exact = sum((F(float(A[i, k])) * F(float(B[k, j])) for k in range(3)), F(0))
+            assert Cb[i, j] != Cs[i, j]
+            assert abs(three - exact) < abs(one - exact)
+
+
 def _bf16_exact(x: np.float32) -> np.float32:
     """Nearest bfloat16 by brute force over the two truncation neighbours."""
     b = int(np.array([x], np.float32).view(np.uint32)[0])

@@ -128,6 +128,26 @@ def test_adam_first_step_is_signed_lr():
         assert np.allclose(m[k], 0.1 * g[k]) and np.allclose(v[k], 0.001 * g[k] ** 2)
 
 
+def test_adam_bias_correction_over_five_steps():
+    # a constant gradient g gives m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2,
+    # so with bias correction every step t = 1..5 moves each parameter by
+    # exactly lr * g / (|g| + eps) up to rounding
+    P = _params()
+    g = {k: synth.uniform_pm1(14, i, v.size).astype(np.float64).reshape(v.shape) + 0.01
+         for i, (k, v) in enumerate(P.items())}
+    m, v = mlp.zeros_like(P), mlp.zeros_like(P)
+    cur = P
+    for t in range(1, 6):
+        nxt, m, v = mlp.adam_step(cur, g, m, v, t, lr=1e-3)
+        for k in mlp.NAMES:
+            assert np.allclose(cur[k] - nxt[k], 1e-3 * g[k] / (np.abs(g[k]) + 1e-8), rtol=1e-9, atol=1e-15), (t, k)
+            assert np.allclose(m[k], (1 - 0.9 ** t) * g[k], rtol=1e-12)
+            assert np.allclose(v[k], (1 - 0.999 ** t) * g[k] ** 2, rtol=1e-12)
+        cur = nxt
+    for k in mlp.NAMES:
+        assert np.allclose(P[k] - cur[k], 5e-3 * g[k] / (np.abs(g[k]) + 1e-8), rtol=1e-9, atol=1e-14)
+
+
 # ------------------------------------------------------------- taskloop ----
 
 @pytest.mark.parametrize("n,g,k", [(100, 7, 0), (100, 0, 7), (100, 30, 5), (100, 0, 500), (5, 10, 0),
