@@ -463,37 +463,27 @@ def bench_matmul(torch, ctx, timer, reps=5):
 
 # ----------------------------------------------------------------- batched
 def make_batched(torch, ctx, seed=12345, n_tasks=2048, lmin=8, lmax=22):
-    """The batched workload: kinds uniform over AXPY / SUM / MATVEC (rows x
-    256), lengths floor(2^U), U ~ U[8, 22]; edges i < j with probability
-    4/(n-1) encoded as depend(out: tok[j]) and depend(in: tok[i])."""
-    kinds = synth.int_range(seed, 100, n_tasks, 0, 3)
-    u = synth.uniform01_f64(seed, 101, n_tasks)
-    lens = np.floor(2.0 ** (lmin + (lmax - lmin) * u)).astype(np.int64)
-    p = 4.0 / (n_tasks - 1)
-    preds = []
-    for j in range(n_tasks):
-        r = synth.uniform01_f64(seed, 1000 + j, max(j, 1))[:j]
-        preds.append([int(i) for i in np.nonzero(r < p)[0]])
+    """The batched workload (the seeded recipe in synth.batched_spec: kinds
+    uniform over AXPY / SUM / MATVEC (rows x 256), lengths floor(2^U),
+    U ~ U[8, 22]; edges i < j with probability 4/(n-1) encoded as
+    depend(out: tok[j]) and depend(in: tok[i])), generated on the device."""
+    kinds, lens, preds = synth.batched_spec(seed, n_tasks, lmin, lmax)
     tasks, bytes_alg = [], 0
-    for j in range(n_tasks):
-        L = int(lens[j])
-        k = int(kinds[j])
-        if k == 0:
-            x = synth.uniform_pm1_torch(seed, 10 * j + 1, L, device="cuda")
-            y = synth.uniform_pm1_torch(seed, 10 * j + 2, L, device="cuda")
-            tasks.append(("axpy", L, {"x": x, "y": y, "y0": y.clone()}))
+    for j, (k, L) in enumerate(zip(kinds, lens)):
+        d = synth.batched_inputs_torch(seed, j, k, L, device="cuda")
+        if k == "axpy":
+            d["y0"] = d["y"].clone()
+            tasks.append(("axpy", L, d))
             bytes_alg += 12 * L
-        elif k == 1:
-            x = synth.uniform_pm1_torch(seed, 10 * j + 1, L, device="cuda")
-            r = torch.zeros(1, dtype=torch.float64, device="cuda")
-            tasks.append(("sum", L, {"x": x, "r": r}))
+        elif k == "sum":
+            d["r"] = torch.zeros(1, dtype=torch.float64, device="cuda")
+            tasks.append(("sum", L, d))
             bytes_alg += 4 * L
         else:
-            rows = max(1, L // 256)
-            A = synth.uniform_pm1_torch(seed, 10 * j + 1, rows * 256, device="cuda")
-            x = synth.uniform_pm1_torch(seed, 10 * j + 2, 256, device="cuda")
-            y = torch.zeros(rows, device="cuda")
-            tasks.append(("matvec", rows, {"A": A, "x": x, "y": y}))
+            rows = synth.batched_rows(L)
+            d["A"] = d["A"].reshape(-1)
+            d["y"] = torch.zeros(rows, device="cuda")
+            tasks.append(("matvec", rows, d))
             bytes_alg += 4 * rows * 256 + 4 * rows + 4 * 256
     return tasks, preds, bytes_alg
 

@@ -120,3 +120,22 @@ def run_task(kind: str, args: dict):
 def run_in_order(tasks):
     """Run a list of (kind, args) tasks in creation (index) order."""
     return [run_task(k, a) for k, a in tasks]
+
+
+def batched_task_expected(seed: int, j: int, kind: str, L: int):
+    """Expected result of task j of the seeded batched workload: its inputs
+    are regenerated on the host from the seeded generators (nothing comes
+    from the GPU) and its loop runs as its serial elision. Returns
+    (kind, result dict, sum |x| for SUM tasks else 0.0); a module-level
+    function so that a pool of worker processes can run it."""
+    import synth  # the seeded input generators (no loop arithmetic)
+
+    args = synth.batched_inputs(seed, j, kind, L)
+    res = run_task(kind, args)
+    l1 = bodies.sum_abs_f64(args["x"]) if kind == "sum" else 0.0
+    return kind, res, l1
+
+
+def batched_task_expected_job(job):
+    """batched_task_expected over one (seed, j, kind, L) tuple (for Pool.imap)."""
+    return batched_task_expected(*job)

@@ -889,16 +889,21 @@ upir_status ensure_scratch(upir_ctx *c, upir_loop_obj *lp, int64_t parts) {
     if (st) return st;
   }
   HIPTRY(c, hipStreamSynchronize(c->stream));
-  unsigned char *ns = (unsigned char *)upir_dalloc(c, scratch_bytes(parts));
+  // grow geometrically, so a loop launched with ever more teams retires few buffers
+  const int64_t cap = std::max<int64_t>(parts, 2 * lp->part_cap);
+  unsigned char *ns = (unsigned char *)upir_dalloc(c, scratch_bytes(cap));
   if (!ns) return upir_fail(c, UPIR_ENOMEM, "reduction scratch");
-  upir_status st = clear_scratch(c, lp, ns, parts);
+  upir_status st = clear_scratch(c, lp, ns, cap);
   if (st) {
     upir_dfree(c, ns);
     return st;
   }
-  upir_dfree(c, lp->scratch);
+  // a graph captured earlier still addresses the old block (combiner slots,
+  // dynamic-schedule counters): it is kept until finalize, like the
+  // outgrown fold buffers
+  if (lp->scratch) c->retired.push_back(lp->scratch);
   lp->scratch = ns;
-  lp->part_cap = parts;
+  lp->part_cap = cap;
   return UPIR_OK;
 }
 

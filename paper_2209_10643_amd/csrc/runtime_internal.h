@@ -127,7 +127,7 @@ struct upir_ctx {
   unsigned long long *fold_buf[2] = {nullptr, nullptr};
   int64_t fold_cap = 0;                  // partials per buffer
   int fold_flip = 0;
-  std::vector<void *> retired;           // outgrown fold buffers (graphs may use them)
+  std::vector<void *> retired;           // outgrown fold buffers and loop scratch (graphs may use them)
 };
 
 // helpers shared by the runtime translation units

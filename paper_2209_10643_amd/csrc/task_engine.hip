@@ -438,32 +438,41 @@ upir_status upir_plain_trace_start(upir_ctx *c) {
   return UPIR_OK;
 }
 
-upir_status upir_plain_trace(upir_ctx *c, int64_t task, hipStream_t s) {
+// Predecessor lists of every pending task, concatenated in task order, in
+// one device array (the plain executor's trace kernels read their task's
+// slice). Copied before any task runs and before a graph capture starts, so
+// no copy or synchronisation happens while tasks are enqueued or captured.
+upir_status upir_plain_trace_preds(upir_ctx *c, int32_t **dev_out, std::vector<int64_t> &offsets) {
+  *dev_out = nullptr;
+  const size_t n = c->tasks.size();
+  offsets.assign(n + 1, 0);
+  for (size_t j = 0; j < n; ++j) offsets[j + 1] = offsets[j] + (int64_t)c->tasks[j].preds.size();
+  if (offsets[n] == 0) return UPIR_OK;
+  if (offsets[n] >= (1LL << 31)) return upir_fail(c, UPIR_EINVAL, "too many task edges to trace");
+  std::vector<int32_t> hp((size_t)offsets[n]);
+  for (size_t j = 0; j < n; ++j)
+    for (size_t i = 0; i < c->tasks[j].preds.size(); ++i) hp[(size_t)offsets[j] + i] = (int32_t)c->tasks[j].preds[i];
+  int32_t *dp = (int32_t *)upir_dalloc(c, hp.size() * 4);
+  if (!dp) return upir_fail(c, UPIR_ENOMEM, "trace preds");
+  hipError_t e = hipMemcpyAsync(dp, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    upir_dfree(c, dp);
+    return upir_hipfail(c, e, "trace preds copy");
+  }
+  *dev_out = dp;
+  return UPIR_OK;
+}
+
+// Token and stamps of task `task` after its kernel, on stream s; its
+// predecessors are preds[0 .. np).
+upir_status upir_plain_trace(upir_ctx *c, int64_t task, const int32_t *preds, int32_t np, hipStream_t s) {
   unsigned long long *clock = nullptr;
   upir_status st = plain_trace_buf(c, &clock);
   if (st) return st;
-  const auto &preds = c->tasks[task].preds;
-  // predecessor ids travel in a small device array owned by the task list
-  int32_t *dp = nullptr;
-  if (!preds.empty()) {
-    dp = (int32_t *)upir_dalloc(c, preds.size() * 4);
-    if (!dp) return upir_fail(c, UPIR_ENOMEM, "trace preds");
-    std::vector<int32_t> hp(preds.begin(), preds.end());
-    hipError_t e = hipMemcpyAsync(dp, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      upir_dfree(c, dp);
-      return upir_hipfail(c, e, "trace preds copy");
-    }
-  }
-  hipLaunchKernelGGL(k_plain_trace, dim3(1), dim3(64), 0, s, (int32_t)task, dp, (int32_t)preds.size(),
-                     c->trace.tokens, c->trace.start_stamp, c->trace.done_stamp, clock);
+  hipLaunchKernelGGL(k_plain_trace, dim3(1), dim3(64), 0, s, (int32_t)task, preds, np, c->trace.tokens,
+                     c->trace.start_stamp, c->trace.done_stamp, clock);
   hipError_t e = hipGetLastError();
-  if (dp) {
-    hipError_t e2 = hipStreamSynchronize(s);
-    upir_dfree(c, dp);
-    if (e == hipSuccess) e = e2;
-  }
   if (e != hipSuccess) return upir_hipfail(c, e, "trace kernel");
   return UPIR_OK;
 }

@@ -17,8 +17,11 @@
 using namespace upir;
 
 upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **gout);  // task_engine.hip
-upir_status upir_plain_trace(upir_ctx *c, int64_t task, hipStream_t s);               // task_engine.hip
+upir_status upir_plain_trace(upir_ctx *c, int64_t task, const int32_t *preds, int32_t np,
+                             hipStream_t s);                                          // task_engine.hip
 upir_status upir_plain_trace_start(upir_ctx *c);                                      // task_engine.hip
+upir_status upir_plain_trace_preds(upir_ctx *c, int32_t **dev_out,
+                                   std::vector<int64_t> &offsets);                    // task_engine.hip
 
 static bool task_body_ok(int32_t k) {
   return k == UPIR_BODY_AXPY || k == UPIR_BODY_SUM || k == UPIR_BODY_MATVEC || k == UPIR_BODY_COVER;
@@ -194,10 +197,15 @@ static upir_loop_obj task_view(const TaskRec &t) {
 // order is a topological order, so every event waited for has been recorded.
 static int task_queue(const TaskRec &t) { return !t.loop ? (t.dir == UPIR_TO_DEVICE ? 1 : 2) : 0; }
 
-static upir_status run_plain(upir_ctx *c) {
+static bool tracing_on(const upir_ctx *c) { return c->trace.tokens || c->trace.start_stamp || c->trace.done_stamp; }
+
+// Runs (or, during a capture, records) every pending task. With tracing on,
+// `tpreds` holds the predecessor lists on the device (upir_plain_trace_preds,
+// made before this call) and `toff` their offsets.
+static upir_status run_plain(upir_ctx *c, const int32_t *tpreds, const std::vector<int64_t> &toff) {
   const size_t n = c->tasks.size();
   const bool copies = has_copy_tasks(c);
-  const bool tracing = c->trace.tokens || c->trace.start_stamp || c->trace.done_stamp;
+  const bool tracing = tracing_on(c);
   std::vector<hipEvent_t> ev;
   auto cleanup = [&]() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -259,7 +267,10 @@ static upir_status run_plain(upir_ctx *c) {
       st = resolve_plan(c, &t.spmd, lp, pl);
       if (!st) st = launch_plan(c, lp, pl, true);
     }
-    if (!st && tracing) st = upir_plain_trace(c, (int64_t)j, s);
+    if (!st && tracing) {
+      const int32_t np = (int32_t)(toff[j + 1] - toff[j]);
+      st = upir_plain_trace(c, (int64_t)j, np ? tpreds + toff[j] : nullptr, np, s);
+    }
     if (!st && copies && hipEventRecord(ev[j], s) != hipSuccess) st = upir_fail(c, UPIR_EHIP, "task event");
     if (st) {
       if (copies) {
@@ -312,8 +323,18 @@ extern "C" upir_status upir_taskwait(upir_ctx *c, int32_t mode) {
     return upir_fail(c, UPIR_EUNSUPPORTED, "data_update tasks run with taskwait PLAIN");
   upir_status st = settle(c);  // a deferred fold of an earlier loop runs before the tasks
   if (st) return st;
-  st = mode == UPIR_TASKWAIT_PLAIN ? run_plain(c) : upir_batched_run(c, false, nullptr);
-  if (st == UPIR_OK) st = deliver_task_results(c);
+  if (mode == UPIR_TASKWAIT_PLAIN) {
+    int32_t *tpreds = nullptr;
+    std::vector<int64_t> toff;
+    if (tracing_on(c)) st = upir_plain_trace_preds(c, &tpreds, toff);
+    if (!st) st = run_plain(c, tpreds, toff);
+    if (st == UPIR_OK) st = deliver_task_results(c);  // synchronises: the trace kernels are done
+    else (void)hipStreamSynchronize(c->stream);
+    upir_dfree(c, tpreds);
+  } else {
+    st = upir_batched_run(c, false, nullptr);
+    if (st == UPIR_OK) st = deliver_task_results(c);
+  }
   clear_tasks(c);
   return st;
 }
@@ -355,15 +376,26 @@ extern "C" upir_status upir_taskwait_graph(upir_ctx *c, int32_t mode, upir_graph
       clear_tasks(c);
       return upir_hipfail(c, e, "taskwait_graph");
     }
-    st = upir_graph_begin(c);
+    // the trace's predecessor lists go to the device before the capture; the
+    // graph owns that buffer
+    int32_t *tpreds = nullptr;
+    std::vector<int64_t> toff;
+    if (tracing_on(c)) st = upir_plain_trace_preds(c, &tpreds, toff);
+    if (st == UPIR_OK) st = upir_graph_begin(c);
     if (st == UPIR_OK) {
-      upir_status rs = run_plain(c);
+      upir_status rs = run_plain(c, tpreds, toff);
       upir_graph_h g = nullptr;
       st = upir_graph_end(c, &g);
       if (rs) st = rs;
-      if (st == UPIR_OK) *out = g;
-      else if (g) upir_graph_destroy(c, g);
+      if (st == UPIR_OK) {
+        if (tpreds) g->owned.push_back(tpreds);
+        tpreds = nullptr;
+        *out = g;
+      } else if (g) {
+        upir_graph_destroy(c, g);
+      }
     }
+    upir_dfree(c, tpreds);
   }
   clear_tasks(c);
   return st;

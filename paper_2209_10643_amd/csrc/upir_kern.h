@@ -7,10 +7,11 @@
 // path that owns exactly the same iterations.
 //
 // Reduction (sec. 5; sec. 3.1 on fusing a reduction with the region's
-// barrier): lane values are combined inside a wavefront with cross-lane
-// shuffles, across the wavefronts of a workgroup through LDS, and across
-// workgroups in float64 (or exact int64) by the last workgroup to arrive,
-// which reads every workgroup's partial in a fixed order.
+// barrier): lane values are combined inside a wavefront by DPP steps (lane
+// shuffles for a partial last wavefront), across the wavefronts of a
+// workgroup through LDS, and across workgroups in float64 (or exact int64)
+// by the last workgroup launched, which reads every workgroup's partial in a
+// fixed order.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -270,15 +271,20 @@ __device__ inline T read_lane63(T v) {
   }
 }
 
-// Reduction over the 64 lanes, returned to every lane; a fixed tree, so the
-// result is deterministic. Workgroups of whole wavefronts (every lane
-// active) use DPP steps: pairs and quads, the two halves of each row of 16
-// lanes, then rows 0 + 1 and 2 + 3 and finally all four rows into lane 63.
-// Other workgroups use a butterfly over lane shuffles (xor 32, 16, ..., 1).
+// Reduction over the lanes of a wavefront, returned to every lane; a fixed
+// tree, so the result is deterministic. Wavefronts of a workgroup made of
+// whole wavefronts (every lane present) use DPP steps: pairs and quads, the
+// two halves of each row of 16 lanes, then rows 0 + 1 and 2 + 3 and finally
+// all four rows into lane 63. The last wavefront of any other workgroup has
+// only `act` < 64 lanes (lanes 0 .. act-1); there a butterfly over lane
+// shuffles (xor 32, 16, ..., 1) takes the op's identity for every partner
+// lane >= act (such a lane does not exist and its register is undefined), so
+// lane 0 ends with the reduction over the present lanes, which is then read
+// back from lane 0 by every lane.
 template <class T>
 __device__ inline T wave_reduce(int op, T v) {
+  const T id = red_identity<T>(op);
   if (blockDim.x % WAVE == 0) {
-    const T id = red_identity<T>(op);
     v = red_apply(op, v, dpp_move<0xB1, 0xF>(v, id));   // quad_perm [1,0,3,2]
     v = red_apply(op, v, dpp_move<0x4E, 0xF>(v, id));   // quad_perm [2,3,0,1]
     v = red_apply(op, v, dpp_move<0x141, 0xF>(v, id));  // row_half_mirror
@@ -287,9 +293,15 @@ __device__ inline T wave_reduce(int op, T v) {
     v = red_apply(op, v, dpp_move<0x143, 0xC>(v, id));  // row_bcast:31 into rows 2 and 3
     return read_lane63(v);
   }
+  const int lane = (int)(threadIdx.x % WAVE);
+  const int first = (int)(threadIdx.x - (unsigned)lane);
+  const int act = (int)blockDim.x - first < WAVE ? (int)blockDim.x - first : WAVE;
 #pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) v = red_apply(op, v, __shfl_xor(v, s, WAVE));
-  return v;
+  for (int s = 32; s >= 1; s >>= 1) {
+    const T o = __shfl_xor(v, s, WAVE);
+    v = red_apply(op, v, (lane ^ s) < act ? o : id);
+  }
+  return __shfl(v, 0, WAVE);
 }
 
 // Block reduce: every thread passes its value; returns the block value in

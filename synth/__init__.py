@@ -134,3 +134,57 @@ def uniform_01_torch(seed: int, stream: int, n: int, start: int = 0, device="cpu
     import torch
     k = _lsr(torch, hash_u64_torch(seed, stream, n, start, device), 40)
     return (k.to(torch.float64) * 2.0 ** -24).to(torch.float32)
+
+
+# --------------------------------------------------------------------------
+# The batched-task workload: many uneven 1-D loops with random depend edges.
+# Only the recipe of the inputs (kinds, lengths, edges, values) lives here.
+# --------------------------------------------------------------------------
+
+BATCHED_KINDS = ("axpy", "sum", "matvec")
+
+
+def batched_spec(seed: int, n_tasks: int, lmin: int = 8, lmax: int = 22, p_edge: float | None = None):
+    """Task j: kind uniform over AXPY / SUM / MATVEC (stream 100), length
+    floor(2**u) with u uniform in [lmin, lmax] (stream 101; a MATVEC of length
+    L is floor(L / 256) rows (at least one) of 256 columns), and an edge i -> j
+    for each i < j with probability p_edge (default 4 / (n_tasks - 1), i.e. two
+    successors per task on average; stream 1000 + j).
+    Returns (kinds, lengths, preds)."""
+    kinds = [BATCHED_KINDS[int(k)] for k in int_range(seed, 100, n_tasks, 0, 3)]
+    u = uniform01_f64(seed, 101, n_tasks)
+    lens = [int(v) for v in np.floor(2.0 ** (lmin + (lmax - lmin) * u)).astype(np.int64)]
+    p = p_edge if p_edge is not None else 4.0 / max(1, n_tasks - 1)
+    preds = []
+    for j in range(n_tasks):
+        r = uniform01_f64(seed, 1000 + j, max(j, 1))[:j]
+        preds.append([int(i) for i in np.nonzero(r < p)[0]])
+    return kinds, lens, preds
+
+
+def batched_rows(L: int) -> int:
+    return max(1, L // 256)
+
+
+def batched_inputs(seed: int, j: int, kind: str, L: int) -> dict:
+    """Host inputs of task j: AXPY x, y (streams 10j+1, 10j+2) and a = 2.5;
+    SUM x (stream 10j+1); MATVEC A (rows x 256, stream 10j+1) and x (256,
+    stream 10j+2). All uniform[-1, 1) on the 2**-23 grid."""
+    if kind == "axpy":
+        return {"a": 2.5, "x": uniform_pm1(seed, 10 * j + 1, L), "y": uniform_pm1(seed, 10 * j + 2, L)}
+    if kind == "sum":
+        return {"x": uniform_pm1(seed, 10 * j + 1, L)}
+    rows = batched_rows(L)
+    return {"A": uniform_pm1(seed, 10 * j + 1, rows * 256).reshape(rows, 256), "x": uniform_pm1(seed, 10 * j + 2, 256)}
+
+
+def batched_inputs_torch(seed: int, j: int, kind: str, L: int, device="cuda") -> dict:
+    """The same values as batched_inputs, generated by torch on `device`."""
+    if kind == "axpy":
+        return {"a": 2.5, "x": uniform_pm1_torch(seed, 10 * j + 1, L, device=device),
+                "y": uniform_pm1_torch(seed, 10 * j + 2, L, device=device)}
+    if kind == "sum":
+        return {"x": uniform_pm1_torch(seed, 10 * j + 1, L, device=device)}
+    rows = batched_rows(L)
+    return {"A": uniform_pm1_torch(seed, 10 * j + 1, rows * 256, device=device).reshape(rows, 256),
+            "x": uniform_pm1_torch(seed, 10 * j + 2, 256, device=device)}

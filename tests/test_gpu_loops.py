@@ -14,6 +14,7 @@ import pytest
 
 import synth
 from oracle import bodies, loops as oloops
+from oracle import reduce as oreduce
 from paper_2209_10643_amd import helpers as H
 from paper_2209_10643_amd import upir as U
 
@@ -174,6 +175,82 @@ def test_float_reduce_max_min_exact(ctx):
     U.upir_reduce(ctx.h, U.UPIR_RED_SUM, U.UPIR_DT_F64, dev(v.astype(np.float64)).data_ptr(), len(v), None, None,
                   C.byref(red))
     assert abs(res[0] - bodies.sum_f64(v)) <= 1e-12 * bodies.sum_abs_f64(v)
+
+
+# A team of U units with U % 64 != 0 ends in a partial wavefront (or is one,
+# for U < 64). Lanes past the end do not exist: the wavefront reduction must
+# take the op's identity for them, never 0 or an undefined register. MIN
+# over positive data and MAX over negative data see a wrong 0 at once; init
+# is the op's identity so the data alone decide the result.
+PARTIAL_UNITS = [32, 96, 100]
+
+
+@pytest.mark.parametrize("units", PARTIAL_UNITS)
+@pytest.mark.parametrize("pol", [U.UPIR_SCHED_STATIC, U.UPIR_SCHED_STATIC_CHUNK])
+def test_partial_wavefront_float_min_max(ctx, units, pol):
+    note(f"partial wavefront float units={units} pol={pol}")
+    n = 10007
+    pos = synth.uniform_01(31, 0, n) + np.float32(0.5)   # all in [0.5, 1.5)
+    neg = -pos
+    sched = H.make_sched(pol, 4 if pol == U.UPIR_SCHED_STATIC_CHUNK else 0)
+    spmd = H.make_spmd(7, units)
+    for data, op, init, want in ((pos, U.UPIR_RED_MIN, math.inf, float(pos.min())),
+                                 (neg, U.UPIR_RED_MAX, -math.inf, float(neg.max()))):
+        t, r = dev(data), dbl()
+        red = H.make_red(op, r.data_ptr(), init=init)
+        lp = ctx.loop(U.UPIR_BODY_SUM, U.upir_sum_args(t.data_ptr(), U.UPIR_DT_F32, 0), [(0, n, 1)], sched, red)
+        ctx.launch(lp, spmd)
+        ctx.sync()
+        ctx.free(lp)
+        assert r.item() == want == oreduce.reduce("min" if op == U.UPIR_RED_MIN else "max", data), (units, op)
+    # AXPY loop reducing its outputs y' (all positive: a x + y with x, y >= 0.5)
+    x, y = pos, synth.uniform_01(31, 1, n) + np.float32(0.5)
+    tx, ty, r = dev(x), dev(y), dbl()
+    lp = ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, tx.data_ptr(), ty.data_ptr()), [(0, n, 1)], sched,
+                  H.make_red(U.UPIR_RED_MIN, r.data_ptr(), init=math.inf))
+    ctx.launch(lp, spmd)
+    ctx.sync()
+    ctx.free(lp)
+    want = bodies.axpy(2.5, x, y)
+    assert np.array_equal(ty.cpu().numpy(), want)
+    assert r.item() == oreduce.reduce("min", want)
+
+
+@pytest.mark.parametrize("units", PARTIAL_UNITS)
+def test_partial_wavefront_int64_min_max(ctx, units):
+    note(f"partial wavefront int64 units={units}")
+    n = 5003
+    v = synth.int_range(32, 0, n, 1000, 10 ** 9).astype(np.int64)
+    res = (C.c_int64 * 1)()
+    spmd = H.make_spmd(5, units)
+    for data, op, init in ((v, U.UPIR_RED_MIN, 2.0 ** 62), (-v, U.UPIR_RED_MAX, -(2.0 ** 62))):
+        t = dev(data)
+        red = H.make_red(op, C.addressof(res), on_host=True, init=init)
+        U.upir_reduce(ctx.h, op, U.UPIR_DT_I64, t.data_ptr(), n, C.byref(spmd),
+                      C.byref(H.make_sched(U.UPIR_SCHED_STATIC)), C.byref(red))
+        want = oreduce.reduce("min" if op == U.UPIR_RED_MIN else "max", data)
+        assert res[0] == want, (units, op, res[0], want)
+
+
+@pytest.mark.parametrize("units", PARTIAL_UNITS)
+def test_partial_wavefront_jacobi_min_residual(ctx, units):
+    """Jacobi residual MIN through the generic kernel with partial wavefronts:
+    on a field with no fixed point in the interior every |u1 - u0| is > 0."""
+    note(f"partial wavefront jacobi units={units}")
+    N = 67
+    u = synth.uniform_01(33, 0, N * N).reshape(N, N) + np.float32(1.0)
+    u[0, :] = u[-1, :] = 0
+    u[:, 0] = u[:, -1] = 0
+    a, b, r = dev(u), dev(u), dbl()
+    red = H.make_red(U.UPIR_RED_MIN, r.data_ptr(), init=math.inf)
+    lp = ctx.loop(U.UPIR_BODY_JACOBI5, U.upir_jacobi5_args(a.data_ptr(), b.data_ptr(), N),
+                  [(1, N - 1, 1), (1, N - 1, 1)], H.make_sched(U.UPIR_SCHED_STATIC), red)
+    ctx.launch(lp, H.make_spmd(9, units))
+    ctx.sync()
+    ctx.free(lp)
+    wu, wr = bodies.jacobi5(u, 1, op="min")
+    assert np.array_equal(b.cpu().numpy(), wu)
+    assert r.item() == wr[0] and wr[0] > 0
 
 
 # ----------------------------------------------------------- owner maps ----
@@ -402,6 +479,35 @@ def test_jacobi_graph_replays(ctx):
     for got_u, got_r in outs:
         assert np.array_equal(got_u, want_u)
         assert np.array_equal(got_r, want_r)
+
+
+def test_graph_replay_after_scratch_growth(ctx):
+    """A graph captured with T teams keeps working after an eager launch of
+    the same loop with more teams than its reduction scratch held (the
+    scratch grows; the block the graph addresses must stay alive)."""
+    n = 1 << 20
+    x = synth.uniform_pm1(41, 0, n)
+    t, r = dev(x), dbl()
+    lp = ctx.loop(U.UPIR_BODY_SUM, U.upir_sum_args(t.data_ptr(), U.UPIR_DT_F32, 0), [(0, n, 1)],
+                  H.make_sched(U.UPIR_SCHED_STATIC), H.make_red(U.UPIR_RED_SUM, r.data_ptr()))
+    want, tol = bodies.sum_f64(x), 1e-5 * bodies.sum_abs_f64(x)
+    small, big = H.make_spmd(100, 256), H.make_spmd(9000, 64)
+    ctx.launch(lp, small)  # eager first, so nothing has to grow during capture
+    ctx.sync()
+    ctx.graph_begin()
+    ctx.launch(lp, small)
+    g = ctx.graph_end()
+    for k in range(3):
+        r.zero_()
+        ctx.launch(lp, big)  # 9000 workgroups: more slots than the capture's block
+        ctx.sync()
+        assert abs(r.item() - want) <= tol, ("eager", k)
+        r.zero_()
+        ctx.graph_launch(g)
+        ctx.sync()
+        assert abs(r.item() - want) <= tol, ("replay", k)
+    ctx.graph_destroy(g)
+    ctx.free(lp)
 
 
 # --------------------------------------------------------------- matvec ----

@@ -43,29 +43,11 @@ def dev(a):
 
 
 def make_workload(seed, n, lmin=8, lmax=16, p_edge=None):
-    """Task kinds uniform over AXPY / SUM / MATVEC, lengths floor(2^U) with
-    U uniform in [lmin, lmax], edges i < j with probability 4/(n-1)."""
-    kinds = synth.int_range(seed, 100, n, 0, 3)
-    u = synth.uniform01_f64(seed, 101, n)
-    lens = np.floor(2.0 ** (lmin + (lmax - lmin) * u)).astype(np.int64)
-    p = p_edge if p_edge is not None else 4.0 / max(1, n - 1)
-    preds = []
-    for j in range(n):
-        r = synth.uniform01_f64(seed, 1000 + j, max(j, 1))[:j]
-        preds.append([int(i) for i in np.nonzero(r < p)[0]])
-    specs = []
-    for j in range(n):
-        kind = ("axpy", "sum", "matvec")[int(kinds[j])]
-        L = int(lens[j])
-        if kind == "axpy":
-            specs.append((kind, {"a": 2.5, "x": synth.uniform_pm1(seed, 10 * j + 1, L),
-                                 "y": synth.uniform_pm1(seed, 10 * j + 2, L)}))
-        elif kind == "sum":
-            specs.append((kind, {"x": synth.uniform_pm1(seed, 10 * j + 1, L)}))
-        else:
-            rows = max(1, L // 256)
-            specs.append((kind, {"A": synth.uniform_pm1(seed, 10 * j + 1, rows * 256).reshape(rows, 256),
-                                 "x": synth.uniform_pm1(seed, 10 * j + 2, 256)}))
+    """The seeded batched recipe (kinds uniform over AXPY / SUM / MATVEC,
+    lengths floor(2^u) with u uniform in [lmin, lmax], edges i < j with
+    probability 4/(n-1)) at a reduced size, with host inputs."""
+    kinds, lens, preds = synth.batched_spec(seed, n, lmin, lmax, p_edge)
+    specs = [(k, synth.batched_inputs(seed, j, k, L)) for j, (k, L) in enumerate(zip(kinds, lens))]
     return specs, preds
 
 
@@ -184,6 +166,31 @@ def test_batched_graph_replays(ctx):
                 assert np.array_equal(bufs[j][1].cpu().numpy(), cur[j]["y"])
         got_tok = [int(v) & (2 ** 64 - 1) for v in tok.cpu().numpy().tolist()]
         assert got_tok == want_tok
+    ctx.graph_destroy(g)
+    for h in handles:
+        ctx.free(h)
+
+
+def test_plain_graph_with_trace_replays(ctx):
+    """The plain executor captured in a graph with the trace on: the
+    predecessor lists reach the device before the capture and the graph owns
+    them, so every replay writes the oracle's tokens and edge-ordered stamps."""
+    specs, preds = make_workload(7, 90, lmax=13)
+    handles, bufs, tok = build_tasks(ctx, specs, preds)
+    n = len(specs)
+    start = torch.zeros(n, dtype=torch.int64, device="cuda")
+    done = torch.zeros(n, dtype=torch.int64, device="cuda")
+    ctx.set_trace(tok.data_ptr(), start.data_ptr(), done.data_ptr())
+    g = ctx.taskwait_graph(U.UPIR_TASKWAIT_PLAIN)
+    ctx.set_trace()
+    want_tok = otasks.tokens(preds)
+    for rep in range(3):
+        tok.zero_()
+        ctx.graph_launch(g)
+        ctx.sync()
+        got_tok = [int(v) & (2 ** 64 - 1) for v in tok.cpu().numpy().tolist()]
+        assert got_tok == want_tok, rep
+        stamps_ok(preds, start.cpu().numpy(), done.cpu().numpy())
     ctx.graph_destroy(g)
     for h in handles:
         ctx.free(h)
