@@ -2,8 +2,10 @@
 
     python -m paper_2209_10643_amd.build [-j N]
 
-Every HIP source under csrc/ is compiled with hipcc for gfx950 and linked
-into paper_2209_10643_amd/lib/libupir.so. The build always recompiles.
+Every HIP source under csrc/ is compiled with hipcc for gfx950, every plain
+C++ source (host-only logic, also checked under sanitizers on the CPU) with
+the host C++ compiler, and all are linked into
+paper_2209_10643_amd/lib/libupir.so. The build always recompiles.
 """
 from __future__ import annotations
 
@@ -21,6 +23,8 @@ LIB = os.path.join(OUT_DIR, "libupir.so")
 ARCH = os.environ.get("UPIR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("CXX", "g++")
+CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off",                      # bit-exact bodies use explicit fma
@@ -31,15 +35,18 @@ FLAGS = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    if src.endswith(".cpp"):
+        cmd = [CXX, *CXX_FLAGS, "-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        raise RuntimeError(f"compile failed for {src}:\n{r.stderr}")
     return obj
 
 

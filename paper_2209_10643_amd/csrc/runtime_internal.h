@@ -10,6 +10,7 @@
 
 #include "upir.h"
 #include "upir_launch.h"
+#include "task_graph.h"
 
 struct Mapping {
   uintptr_t host;
@@ -65,11 +66,6 @@ struct TaskRec {
   int32_t dir = 0;
 };
 
-struct AddrUse {
-  std::vector<int64_t> writers;  // tasks with out / inout on the address
-  std::vector<int64_t> all;      // every task naming the address
-};
-
 // One timing-table row: features of (loop, candidate) and the measured time.
 struct TuneRow {
   float feat[32];
@@ -112,7 +108,7 @@ struct upir_ctx {
   std::set<upir_graph_obj *> graphs;
   bool capturing = false;
   std::vector<TaskRec> tasks;
-  std::unordered_map<uintptr_t, AddrUse> addr;
+  upir::DepTable deps;                   // depend-clause uses of the pending tasks
   upir_task_trace trace{};
   int num_cus = 256;
   int max_lds = 160 * 1024;

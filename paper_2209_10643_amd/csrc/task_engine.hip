@@ -18,35 +18,25 @@
 //  * every wait is bounded: a workgroup that sees no progress for a long
 //    time raises an error flag and leaves, so the kernel always drains.
 //
-// Cross-XCD visibility uses agent-scope release / acquire (fences around the
-// counters), since the XCDs' L2 caches are not coherent with each other.
+// The XCDs' L2 caches are not coherent with each other. Counters, tokens,
+// results and reduction partials move with relaxed device-coherent (agent
+// scope) atomics, each publisher first waiting for its own accesses to
+// complete; no agent-scope fence (a write-back of the whole L2) is used. A
+// task whose data another task of the graph also touches reads and writes
+// it device-coherently too; a task whose data no other task touches uses
+// plain accesses (non-temporal for large graphs), since its tiles touch
+// disjoint elements and the kernel's end publishes them.
 #include <string.h>
 
 #include <algorithm>
 #include <vector>
 
 #include "runtime_internal.h"
+#include "task_graph.h"
 
 namespace upir {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-struct TaskD {
-  int32_t kind, red_op;
-  int32_t ntiles, part_base;
-  int32_t succ_begin, succ_end;
-  int32_t pred_begin, pred_end;
-  int64_t n, lb, step, tile;
-  float a;
-  int32_t vec;  // 16-byte aligned unit-step vector path allowed
-  const float *x;
-  float *y;
-  const float *A;
-  int64_t cols, lda;
-  int32_t *cnt;
-  double init;
-  double *result;
-};
 
 struct EngineD {
   const TaskD *tasks;
@@ -77,37 +67,50 @@ __device__ inline unsigned long long tick(unsigned long long *p) {
   return __hip_atomic_fetch_add(p, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Task data is read and written with device-coherent accesses: a task may
-// run on another XCD than the task that produced its inputs, and the tiles
-// of one task are spread over XCDs, so values must not stay in (or be read
-// from) one XCD's L2. Pairs of floats travel as 64-bit accesses.
-__device__ inline float2 cld2(const float *p) {
-  const unsigned long long v = __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __builtin_bit_cast(float2, v);
-}
-__device__ inline float cld(const float *p) {
-  return __hip_atomic_load((float *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void cst2(float *p, float2 v) {
-  __hip_atomic_store((unsigned long long *)p, __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void cst(float *p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-
-// 16-byte device-coherent accesses through a buffer resource over one tile's
-// range (cache policy sc1, the level the agent-scope atomics above use; the
-// resource's record count also bounds the accesses to the tile).
+// Task data accesses in one of the MEM_* modes (fixed per instantiation).
+// Coherent: relaxed agent-scope atomics (pairs of floats as 64-bit
+// accesses) and buffer accesses with the sc1 policy, the level those atomics
+// use, so values neither stay in nor come from one XCD's L2. Private: plain
+// accesses; private-nt: with the non-temporal hint.
 typedef float f32x4e __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4e __attribute__((ext_vector_type(4)));
-constexpr int kCoherent = 16;  // sc1
+constexpr int mem_aux(int mem) { return mem == MEM_COHERENT ? 16 : (mem == MEM_PRIVATE_NT ? 2 : 0); }
+
+template <int MEM>
+__device__ inline float ld1(const float *p) {
+  if constexpr (MEM == MEM_COHERENT) return __hip_atomic_load((float *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else if constexpr (MEM == MEM_PRIVATE_NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <int MEM>
+__device__ inline void st1(float *p, float v) {
+  if constexpr (MEM == MEM_COHERENT) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else if constexpr (MEM == MEM_PRIVATE_NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+template <int MEM>
+__device__ inline float2 ld2(const float *p) {
+  if constexpr (MEM == MEM_COHERENT) {
+    const unsigned long long v =
+        __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(float2, v);
+  } else {
+    return float2{ld1<MEM>(p), ld1<MEM>(p + 1)};
+  }
+}
+
+// 16-byte accesses through a buffer resource over one tile's range (the
+// resource's record count also bounds the accesses to the tile).
 __device__ inline __amdgpu_buffer_rsrc_t tile_rsrc(const void *base, int64_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, 0x00020000);
 }
-__device__ inline f32x4e cld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(f32x4e, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kCoherent));
+template <int MEM>
+__device__ inline f32x4e ld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(f32x4e, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, mem_aux(MEM)));
 }
-__device__ inline void cst4(__amdgpu_buffer_rsrc_t r, uint32_t off, f32x4e v) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4e, v), r, off, 0, kCoherent);
+template <int MEM>
+__device__ inline void st4(__amdgpu_buffer_rsrc_t r, uint32_t off, f32x4e v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4e, v), r, off, 0, mem_aux(MEM));
 }
 
 // Reset the mutable engine state (a kernel, so graphs hold no memset node)
@@ -139,7 +142,7 @@ __device__ inline void fold_op(float &acc, float v) {
   if (OP != RED_NONE) acc = red_apply(OP, acc, v);
 }
 
-template <int OP>
+template <int OP, int MEM>
 __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
   constexpr int UN = 4;
   const int64_t lo = tile * t.tile;
@@ -155,14 +158,14 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
       for (int64_t c0 = 0; c0 < t.cols; c0 += 256) {
         const int64_t c = c0 + 4 * lane;
         if (t.vec && c + 3 < t.cols) {
-          const float2 a0 = cld2(a + c), a1 = cld2(a + c + 2), x0 = cld2(t.x + c), x1 = cld2(t.x + c + 2);
+          const float2 a0 = ld2<MEM>(a + c), a1 = ld2<MEM>(a + c + 2), x0 = ld2<MEM>(t.x + c), x1 = ld2<MEM>(t.x + c + 2);
           s = __builtin_fmaf(a0.x, x0.x, s);
           s = __builtin_fmaf(a0.y, x0.y, s);
           s = __builtin_fmaf(a1.x, x1.x, s);
           s = __builtin_fmaf(a1.y, x1.y, s);
         } else {
           for (int q = 0; q < 4; ++q)
-            if (c + q < t.cols) s = __builtin_fmaf(cld(a + c + q), cld(t.x + c + q), s);
+            if (c + q < t.cols) s = __builtin_fmaf(ld1<MEM>(a + c + q), ld1<MEM>(t.x + c + q), s);
         }
       }
       return s;
@@ -171,12 +174,12 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
     if (t.vec && t.cols == 256 && t.step == 1 && 4 * (hi - lo) * t.lda < (1LL << 31)) {
       // the common shape: four rows in flight per wavefront
       const int c = 4 * lane;
-      const float2 x0 = cld2(t.x + c), x1 = cld2(t.x + c + 2);
+      const float2 x0 = ld2<MEM>(t.x + c), x1 = ld2<MEM>(t.x + c + 2);
       const __amdgpu_buffer_rsrc_t ra = tile_rsrc(t.A + (t.lb + lo) * t.lda, 4 * (hi - lo) * t.lda);
       for (; k + (UN - 1) * nw < hi; k += UN * nw) {
         f32x4e av[UN];
 #pragma unroll
-        for (int u = 0; u < UN; ++u) av[u] = cld4(ra, (uint32_t)(4 * ((k + u * nw - lo) * t.lda + c)));
+        for (int u = 0; u < UN; ++u) av[u] = ld4<MEM>(ra, (uint32_t)(4 * ((k + u * nw - lo) * t.lda + c)));
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
           float s = 0.0f;
@@ -186,7 +189,7 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
           s = __builtin_fmaf(av[u].w, x1.y, s);
           s = wave_reduce(RED_SUM, s);
           if (lane == 0) {
-            cst(t.y + t.lb + k + u * nw, s);
+            st1<MEM>(t.y + t.lb + k + u * nw, s);
             fold_op<OP>(acc, s);
           }
         }
@@ -196,7 +199,7 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
       const int64_t r = t.lb + k * t.step;
       const float s = wave_reduce(RED_SUM, row_dot(r));
       if (lane == 0) {
-        cst(t.y + r, s);
+        st1<MEM>(t.y + r, s);
         fold_op<OP>(acc, s);
       }
     }
@@ -212,8 +215,8 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
         f32x4e xv[UN], yv[UN];
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
-          xv[u] = cld4(rx, (uint32_t)(16 * (m + u * nt)));
-          yv[u] = cld4(ry, (uint32_t)(16 * (m + u * nt)));
+          xv[u] = ld4<MEM>(rx, (uint32_t)(16 * (m + u * nt)));
+          yv[u] = ld4<MEM>(ry, (uint32_t)(16 * (m + u * nt)));
         }
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
@@ -222,7 +225,7 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
           r.y = __builtin_fmaf(t.a, xv[u].y, yv[u].y);
           r.z = __builtin_fmaf(t.a, xv[u].z, yv[u].z);
           r.w = __builtin_fmaf(t.a, xv[u].w, yv[u].w);
-          cst4(ry, (uint32_t)(16 * (m + u * nt)), r);
+          st4<MEM>(ry, (uint32_t)(16 * (m + u * nt)), r);
           fold_op<OP>(acc, r.x);
           fold_op<OP>(acc, r.y);
           fold_op<OP>(acc, r.z);
@@ -230,13 +233,13 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
         }
       }
       for (; m < nc; m += nt) {
-        const f32x4e xv = cld4(rx, (uint32_t)(16 * m)), yv = cld4(ry, (uint32_t)(16 * m));
+        const f32x4e xv = ld4<MEM>(rx, (uint32_t)(16 * m)), yv = ld4<MEM>(ry, (uint32_t)(16 * m));
         f32x4e r;
         r.x = __builtin_fmaf(t.a, xv.x, yv.x);
         r.y = __builtin_fmaf(t.a, xv.y, yv.y);
         r.z = __builtin_fmaf(t.a, xv.z, yv.z);
         r.w = __builtin_fmaf(t.a, xv.w, yv.w);
-        cst4(ry, (uint32_t)(16 * m), r);
+        st4<MEM>(ry, (uint32_t)(16 * m), r);
         fold_op<OP>(acc, r.x);
         fold_op<OP>(acc, r.y);
         fold_op<OP>(acc, r.z);
@@ -247,7 +250,7 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
       for (; m + (2 * UN - 1) * nt < nc; m += 2 * UN * nt) {
         f32x4e xv[2 * UN];
 #pragma unroll
-        for (int u = 0; u < 2 * UN; ++u) xv[u] = cld4(rx, (uint32_t)(16 * (m + u * nt)));
+        for (int u = 0; u < 2 * UN; ++u) xv[u] = ld4<MEM>(rx, (uint32_t)(16 * (m + u * nt)));
 #pragma unroll
         for (int u = 0; u < 2 * UN; ++u) {
           fold_op<OP>(acc, xv[u].x);
@@ -257,7 +260,7 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
         }
       }
       for (; m < nc; m += nt) {
-        const f32x4e xv = cld4(rx, (uint32_t)(16 * m));
+        const f32x4e xv = ld4<MEM>(rx, (uint32_t)(16 * m));
         fold_op<OP>(acc, xv.x);
         fold_op<OP>(acc, xv.y);
         fold_op<OP>(acc, xv.z);
@@ -270,11 +273,11 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
     for (int64_t k = lo + 4 * nc + tid; k < hi; k += nt) {  // ragged end of the tile
       const int64_t i = t.lb + k;
       if (t.kind == UPIR_BODY_AXPY) {
-        const float r = __builtin_fmaf(t.a, cld(t.x + i), cld(t.y + i));
-        cst(t.y + i, r);
+        const float r = __builtin_fmaf(t.a, ld1<MEM>(t.x + i), ld1<MEM>(t.y + i));
+        st1<MEM>(t.y + i, r);
         fold_op<OP>(acc, r);
       } else if (t.kind == UPIR_BODY_SUM) {
-        fold_op<OP>(acc, cld(t.x + i));
+        fold_op<OP>(acc, ld1<MEM>(t.x + i));
       } else {
         atomicAdd(&t.cnt[k], 1);
       }
@@ -284,23 +287,32 @@ __device__ inline void run_tile_op(const TaskD &t, int64_t tile, float &acc) {
   for (int64_t k = lo + tid; k < hi; k += nt) {
     const int64_t i = t.lb + k * t.step;
     if (t.kind == UPIR_BODY_AXPY) {
-      const float r = __builtin_fmaf(t.a, cld(t.x + i), cld(t.y + i));
-      cst(t.y + i, r);
+      const float r = __builtin_fmaf(t.a, ld1<MEM>(t.x + i), ld1<MEM>(t.y + i));
+      st1<MEM>(t.y + i, r);
       fold_op<OP>(acc, r);
     } else if (t.kind == UPIR_BODY_SUM) {
-      fold_op<OP>(acc, cld(t.x + i));
+      fold_op<OP>(acc, ld1<MEM>(t.x + i));
     } else {
       atomicAdd(&t.cnt[k], 1);
     }
   }
 }
 
-__device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
+template <int MEM>
+__device__ inline void run_tile_mem(const TaskD &t, int64_t tile, float &acc) {
   switch (t.red_op) {
-    case RED_SUM: return run_tile_op<RED_SUM>(t, tile, acc);
-    case RED_MAX: return run_tile_op<RED_MAX>(t, tile, acc);
-    case RED_MIN: return run_tile_op<RED_MIN>(t, tile, acc);
-    default: return run_tile_op<RED_NONE>(t, tile, acc);
+    case RED_SUM: return run_tile_op<RED_SUM, MEM>(t, tile, acc);
+    case RED_MAX: return run_tile_op<RED_MAX, MEM>(t, tile, acc);
+    case RED_MIN: return run_tile_op<RED_MIN, MEM>(t, tile, acc);
+    default: return run_tile_op<RED_NONE, MEM>(t, tile, acc);
+  }
+}
+
+__device__ inline void run_tile(const TaskD &t, int64_t tile, float &acc) {
+  switch (t.mem) {
+    case MEM_PRIVATE: return run_tile_mem<MEM_PRIVATE>(t, tile, acc);
+    case MEM_PRIVATE_NT: return run_tile_mem<MEM_PRIVATE_NT>(t, tile, acc);
+    default: return run_tile_mem<MEM_COHERENT>(t, tile, acc);
   }
 }
 
@@ -490,32 +502,12 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
     }
     return UPIR_OK;
   }
-  // ---- host tables
+  // ---- host tables (task_graph.cpp builds and lays them out)
   std::vector<TaskD> td(n);
-  std::vector<int32_t> succ_cnt(n, 0), indeg(n, 0);
-  int64_t parts = 0;
-  for (int32_t j = 0; j < n; ++j) {
-    for (int64_t p : c->tasks[j].preds) succ_cnt[p]++;
-    indeg[j] = (int32_t)c->tasks[j].preds.size();
-  }
-  std::vector<int32_t> succ_off(n + 1, 0), pred_off(n + 1, 0);
-  for (int32_t j = 0; j < n; ++j) {
-    succ_off[j + 1] = succ_off[j] + succ_cnt[j];
-    pred_off[j + 1] = pred_off[j] + indeg[j];
-  }
-  std::vector<int32_t> succ(succ_off[n]), pred(pred_off[n]), fill(n, 0);
-  for (int32_t j = 0; j < n; ++j) {
-    int32_t q = pred_off[j];
-    for (int64_t p : c->tasks[j].preds) {
-      pred[q++] = (int32_t)p;
-      succ[succ_off[p] + fill[p]++] = j;
-    }
-  }
-  std::vector<int32_t> init_ready;
-  for (int32_t j = 0; j < n; ++j)
-    if (indeg[j] == 0) init_ready.push_back(j);
+  std::vector<std::vector<int64_t>> preds(n);
   for (int32_t j = 0; j < n; ++j) {
     upir_loop_obj *lp = c->tasks[j].loop;
+    preds[j] = c->tasks[j].preds;
     alignas(16) unsigned char pay[sizeof(MatmulP) + 16];
     upir_status st = resolve_payload(c, lp, pay);
     if (st) return st;
@@ -530,18 +522,7 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
       d.lb += c->tasks[j].lo * d.step;
       d.n = c->tasks[j].hi - c->tasks[j].lo;
     }
-    int64_t tile = task_tile(c, lp);
-    if (lp->kind != UPIR_BODY_MATVEC) tile = std::max<int64_t>(4, (tile + 3) / 4 * 4);
-    d.tile = std::max<int64_t>(1, std::min<int64_t>(tile, 1 << 24));  // tile bytes fit a buffer resource
-    const int64_t nt = std::max<int64_t>(1, (d.n + d.tile - 1) / d.tile);
-    if (nt > (1LL << 30)) return upir_fail(c, UPIR_EINVAL, "task %d has too many tiles", j);
-    d.ntiles = (int32_t)nt;
-    d.part_base = (int32_t)parts;
-    if (d.red_op) parts += nt;
-    d.succ_begin = succ_off[j];
-    d.succ_end = succ_off[j + 1];
-    d.pred_begin = pred_off[j];
-    d.pred_end = pred_off[j + 1];
+    d.tile = task_tile(c, lp);
     if (lp->has_red) {
       d.init = lp->red.init;
       d.result = (double *)(lp->red.result_on_host ? (void *)(lp->scratch + SCR_RESULT) : lp->red.result);
@@ -573,72 +554,37 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
       d.vec = d.step == 1 && lp->loop.dim[0].lb == 0 && (uintptr_t)d.cnt % 16 == 0;
     }
   }
-  if (parts > (1LL << 31)) return upir_fail(c, UPIR_EINVAL, "too many reduction tiles");
-  int64_t total_tiles = 0;
-  for (const TaskD &d : td) total_tiles += d.ntiles;
-  if (total_tiles >= (1LL << 31)) return upir_fail(c, UPIR_EINVAL, "too many tiles");
-  // initially ready tasks take the front of the work list, in task order
-  std::vector<int32_t> init_base(n, -1), init_work;
-  for (int32_t j : init_ready) {
-    init_base[j] = (int32_t)init_work.size();
-    for (int32_t q = 0; q < td[j].ntiles; ++q) init_work.push_back(j);
-  }
-  // ---- device buffer: static tables, then mutable state
-  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t b_tasks = al(sizeof(TaskD) * n), b_succ = al(4 * succ.size() + 4), b_pred = al(4 * pred.size() + 4);
-  const size_t b_iw = al(4 * init_work.size() + 4), b_i32 = al(4 * (size_t)n), b_work = al(4 * (size_t)total_tiles);
-  const size_t static_bytes = b_tasks + b_succ + b_pred + b_iw + 2 * b_i32;
-  const size_t total = static_bytes + 3 * b_i32 + b_work + al(64) + al(8 * (size_t)std::max<int64_t>(parts, 1));
-  std::vector<unsigned char> host(static_bytes, 0);
-  size_t o = 0;
-  memcpy(&host[o], td.data(), sizeof(TaskD) * n);
-  o += b_tasks;
-  if (!succ.empty()) memcpy(&host[o], succ.data(), 4 * succ.size());
-  o += b_succ;
-  if (!pred.empty()) memcpy(&host[o], pred.data(), 4 * pred.size());
-  o += b_pred;
-  if (!init_work.empty()) memcpy(&host[o], init_work.data(), 4 * init_work.size());
-  o += b_iw;
-  memcpy(&host[o], init_base.data(), 4 * (size_t)n);
-  o += b_i32;
-  memcpy(&host[o], indeg.data(), 4 * (size_t)n);
-  unsigned char *dev = (unsigned char *)upir_dalloc(c, total);
-  if (!dev) return upir_fail(c, UPIR_ENOMEM, "task engine tables (%zu bytes)", total);
-  hipError_t e = hipMemcpyAsync(dev, host.data(), static_bytes, hipMemcpyHostToDevice, c->stream);
+  std::vector<unsigned char> host;
+  EngineLayout lay{};
+  std::string why;
+  if (!build_engine_tables(td, preds, host, lay, why)) return upir_fail(c, UPIR_EINVAL, "task engine: %s", why.c_str());
+  const int64_t total_tiles = lay.total_tiles;
+  // ---- device buffer: the static image, then mutable state
+  unsigned char *dev = (unsigned char *)upir_dalloc(c, lay.total_bytes);
+  if (!dev) return upir_fail(c, UPIR_ENOMEM, "task engine tables (%zu bytes)", lay.total_bytes);
+  hipError_t e = hipMemcpyAsync(dev, host.data(), lay.static_bytes, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     upir_dfree(c, dev);
     return upir_hipfail(c, e, "task table copy");
   }
   EngineD E{};
-  o = 0;
-  E.tasks = (const TaskD *)(dev + o);
-  o += b_tasks;
-  E.succ = (const int32_t *)(dev + o);
-  o += b_succ;
-  E.pred = (const int32_t *)(dev + o);
-  o += b_pred;
-  E.init_work = (const int32_t *)(dev + o);
-  o += b_iw;
-  E.init_base = (const int32_t *)(dev + o);
-  o += b_i32;
-  E.indeg0 = (const int32_t *)(dev + o);
-  o += b_i32;
-  E.indeg = (int32_t *)(dev + o);
-  o += b_i32;
-  E.tiles_done = (int32_t *)(dev + o);
-  o += b_i32;
-  E.task_base = (int32_t *)(dev + o);
-  o += b_i32;
-  E.work = (int32_t *)(dev + o);
-  o += b_work;
-  E.ctrl = (int32_t *)(dev + o);
-  E.clock = (unsigned long long *)(dev + o + 16);
-  o += al(64);
-  E.partials = (double *)(dev + o);
+  E.tasks = (const TaskD *)(dev + lay.tasks);
+  E.succ = (const int32_t *)(dev + lay.succ);
+  E.pred = (const int32_t *)(dev + lay.pred);
+  E.init_work = (const int32_t *)(dev + lay.init_work);
+  E.init_base = (const int32_t *)(dev + lay.init_base);
+  E.indeg0 = (const int32_t *)(dev + lay.indeg0);
+  E.indeg = (int32_t *)(dev + lay.indeg);
+  E.tiles_done = (int32_t *)(dev + lay.tiles_done);
+  E.task_base = (int32_t *)(dev + lay.task_base);
+  E.work = (int32_t *)(dev + lay.work);
+  E.ctrl = (int32_t *)(dev + lay.ctrl);
+  E.clock = (unsigned long long *)(dev + lay.ctrl + 16);
+  E.partials = (double *)(dev + lay.partials);
   E.ntasks = n;
   E.total_tiles = (int32_t)total_tiles;
-  E.init_tiles = (int32_t)init_work.size();
+  E.init_tiles = lay.init_tiles;
   E.tok = c->trace.tokens;
   E.tstart = c->trace.start_stamp;
   E.tdone = c->trace.done_stamp;

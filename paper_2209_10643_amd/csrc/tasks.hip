@@ -46,30 +46,6 @@ static upir_status check_task(upir_ctx *c, const upir_spmd *spmd, upir_loop_h lp
   return UPIR_OK;
 }
 
-// Predecessors of a new task (or of every task of a new taskloop) from the
-// depend list, before any of them is recorded.
-static std::vector<int64_t> preds_of(upir_ctx *c, const upir_depend *deps, int32_t ndeps) {
-  std::vector<int64_t> preds;
-  for (int32_t i = 0; i < ndeps; ++i) {
-    auto it = c->addr.find((uintptr_t)deps[i].addr);
-    if (it == c->addr.end()) continue;
-    const AddrUse &u = it->second;
-    const std::vector<int64_t> &src = deps[i].type == UPIR_DEP_IN ? u.writers : u.all;
-    preds.insert(preds.end(), src.begin(), src.end());
-  }
-  std::sort(preds.begin(), preds.end());
-  preds.erase(std::unique(preds.begin(), preds.end()), preds.end());
-  return preds;
-}
-
-static void record_uses(upir_ctx *c, const upir_depend *deps, int32_t ndeps, int64_t id) {
-  for (int32_t i = 0; i < ndeps; ++i) {
-    AddrUse &u = c->addr[(uintptr_t)deps[i].addr];
-    if (u.all.empty() || u.all.back() != id) u.all.push_back(id);
-    if (deps[i].type != UPIR_DEP_IN && (u.writers.empty() || u.writers.back() != id)) u.writers.push_back(id);
-  }
-}
-
 extern "C" upir_status upir_taskloop(upir_ctx *c, const upir_spmd *spmd, upir_loop_h lp, int64_t grainsize,
                                      int64_t num_tasks, const upir_depend *deps, int32_t ndeps, int64_t *first_task,
                                      int64_t *count) {
@@ -91,7 +67,7 @@ extern "C" upir_status upir_taskloop(upir_ctx *c, const upir_spmd *spmd, upir_lo
   }
   if (G > (1 << 20)) return upir_fail(c, UPIR_EINVAL, "taskloop: %lld tasks", (long long)G);
   const int64_t first = (int64_t)c->tasks.size();
-  const std::vector<int64_t> preds = preds_of(c, deps, ndeps);
+  const std::vector<int64_t> preds = c->deps.preds_of(deps, ndeps);
   const int64_t q = G ? n / G : 0, r = G ? n % G : 0;
   for (int64_t t = 0; t < G; ++t) {
     TaskRec rec{sp, lp, preds};
@@ -99,7 +75,7 @@ extern "C" upir_status upir_taskloop(upir_ctx *c, const upir_spmd *spmd, upir_lo
     rec.hi = rec.lo + q + (t < r ? 1 : 0);
     c->tasks.push_back(std::move(rec));
   }
-  for (int64_t t = 0; t < G; ++t) record_uses(c, deps, ndeps, first + t);
+  for (int64_t t = 0; t < G; ++t) c->deps.record(deps, ndeps, first + t);
   if (first_task) *first_task = first;
   if (count) *count = G;
   return UPIR_OK;
@@ -114,8 +90,8 @@ extern "C" upir_status upir_task(upir_ctx *c, const upir_spmd *spmd, upir_loop_h
   if (lp->has_red && lp->red.result_on_host && lp->red.async)
     return upir_fail(c, UPIR_EINVAL, "task: reductions of tasks complete at taskwait; async is meaningless");
   const int64_t id = (int64_t)c->tasks.size();
-  c->tasks.push_back(TaskRec{sp, lp, preds_of(c, deps, ndeps)});
-  record_uses(c, deps, ndeps, id);  // once per address and kind
+  c->tasks.push_back(TaskRec{sp, lp, c->deps.preds_of(deps, ndeps)});
+  c->deps.record(deps, ndeps, id);  // once per address and kind
   if (task_id) *task_id = id;
   return UPIR_OK;
 }
@@ -131,12 +107,12 @@ extern "C" upir_status upir_task_update(upir_ctx *c, void *host, size_t bytes, i
       return upir_fail(c, UPIR_EDEPEND, "task_update: depend %d has type %d", i, deps[i].type);
   if (c->capturing) return upir_fail(c, UPIR_ESTATE, "task creation during graph capture");
   const int64_t id = (int64_t)c->tasks.size();
-  TaskRec rec{upir_spmd{0, 0, UPIR_TARGET_GPU}, nullptr, preds_of(c, deps, ndeps)};
+  TaskRec rec{upir_spmd{0, 0, UPIR_TARGET_GPU}, nullptr, c->deps.preds_of(deps, ndeps)};
   rec.host = host;
   rec.bytes = bytes;
   rec.dir = dir;
   c->tasks.push_back(std::move(rec));
-  record_uses(c, deps, ndeps, id);
+  c->deps.record(deps, ndeps, id);
   if (task_id) *task_id = id;
   return UPIR_OK;
 }
@@ -167,7 +143,7 @@ extern "C" upir_status upir_set_task_trace(upir_ctx *c, const upir_task_trace *t
 
 static void clear_tasks(upir_ctx *c) {
   c->tasks.clear();
-  c->addr.clear();
+  c->deps.clear();
 }
 
 // The loop a task runs: the handle itself, or for a taskloop task a copy
