@@ -253,6 +253,25 @@ upir_status upir_reduce_wait(upir_ctx *ctx, upir_loop_h loop);
  * float data reduce to a double, integer data to an exact int64. */
 upir_status upir_reduce(upir_ctx *ctx, int32_t op, int32_t dtype, const void *dev_in, int64_t n,
                         const upir_spmd *spmd, const upir_sched *sched, upir_reduction *red);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * reduction of upir_reduce, with the same arguments, kernels and results,
+ * that allocates nothing. Its reduction scratch is a static device array of
+ * 256 + 128 x UPIR_REDUCE_NOALLOC_MAX_TEAMS bytes that every GPU the library
+ * runs on holds until the process ends. Differences from upir_reduce:
+ *  - red->result must be a device address (result_on_host = 0; else
+ *    UPIR_EINVAL); the call only enqueues, and the result is defined in
+ *    stream order after the call's kernels (no synchronisation);
+ *  - schedule AUTO resolves to the tuned table or the library default, never
+ *    the cost model (its inference allocates);
+ *  - a resolved launch of more than UPIR_REDUCE_NOALLOC_MAX_TEAMS workgroups
+ *    fails with UPIR_EINVAL before anything is enqueued;
+ *  - all calls on one GPU share the array (each call clears what it uses
+ *    first, with a kernel): calls that may overlap on one GPU (other
+ *    streams, contexts or threads) race and give undefined results. */
+#define UPIR_REDUCE_NOALLOC_MAX_TEAMS 4096
+upir_status upir_reduce_noalloc(upir_ctx *ctx, int32_t op, int32_t dtype, const void *dev_in, int64_t n,
+                                const upir_spmd *spmd, const upir_sched *sched, upir_reduction *red);
 /* The launch geometry and kernel variant the library would use (after AUTO
  * resolution): teams, units and the resolved schedule. */
 upir_status upir_loop_resolve(upir_ctx *ctx, const upir_spmd *spmd, upir_loop_h loop,

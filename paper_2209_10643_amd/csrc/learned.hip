@@ -714,7 +714,7 @@ void candidate_features(upir_ctx *, const upir_loop_obj *lp, const upir_spmd &sp
 // Cost model pick: batch every candidate through one forward pass and take
 // the smallest predicted time. Returns false when the model is off.
 bool model_pick(upir_ctx *c, upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc) {
-  if (!c->model || !c->model_on || c->capturing) return false;
+  if (!c->model || !c->model_on || c->capturing || c->no_alloc) return false;  // inference allocates
   auto cs = candidates(c, lp);
   if (cs.empty()) return false;
   std::vector<float> X(cs.size() * 32);

@@ -114,6 +114,11 @@ extern "C" upir_status upir_init(int device, void *hip_stream, upir_ctx **out) {
     c->num_cus = prop.multiProcessorCount;
     c->max_lds = (int)prop.maxSharedMemoryPerMultiProcessor;
   }
+  if (upir::noalloc_setup(device, &c->noalloc_scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return UPIR_EHIP;
+  }
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -372,12 +377,11 @@ static upir_status validate_sched(upir_ctx *c, const upir_loop &L, const upir_sc
   return UPIR_OK;
 }
 
-extern "C" upir_status upir_loop_parallel(upir_ctx *c, const upir_loop *loop, const upir_sched *sched,
-                                          const upir_body *body, const upir_reduction *red, upir_loop_h *out) {
-  if (!c) return UPIR_EINVAL;
-  if (!loop || !body || !out) return upir_fail(c, UPIR_EINVAL, "loop_parallel: null loop, body or out");
-  *out = nullptr;
-  if (c->capturing) return upir_fail(c, UPIR_ESTATE, "loop_parallel during graph capture");
+// Validate a loop description and fill *lp from it: no allocation, nothing
+// enqueued (scratch and workspace are the caller's business).
+upir_status describe_loop(upir_ctx *c, const upir_loop *loop, const upir_sched *sched, const upir_body *body,
+                          const upir_reduction *red, upir_loop_obj *lp) {
+  if (!loop || !body) return upir_fail(c, UPIR_EINVAL, "loop_parallel: null loop or body");
   const upir_loop &L = *loop;
   if (L.collapse < 1 || L.collapse > 3) return upir_fail(c, UPIR_EINVAL, "collapse %d not in 1..3", L.collapse);
   int64_t cnt[3] = {1, 1, 1};
@@ -439,8 +443,6 @@ extern "C" upir_status upir_loop_parallel(upir_ctx *c, const upir_loop *loop, co
     return upir_fail(c, UPIR_EINVAL, "filter leading dimension");
   if (has_red && R.result_on_host && c->none) return upir_fail(c, UPIR_ESTATE, "host results need a device");
 
-  upir_loop_obj *lp = new (std::nothrow) upir_loop_obj();
-  if (!lp) return upir_fail(c, UPIR_ENOMEM, "loop handle");
   lp->ctx = c;
   lp->loop = L;
   lp->sched = S;
@@ -454,6 +456,24 @@ extern "C" upir_status upir_loop_parallel(upir_ctx *c, const upir_loop *loop, co
   lp->n = (int64_t)n;
   lp->sum_dtype = sum_dtype;
   lp->key = loop_shape_key(lp);
+  return UPIR_OK;
+}
+
+extern "C" upir_status upir_loop_parallel(upir_ctx *c, const upir_loop *loop, const upir_sched *sched,
+                                          const upir_body *body, const upir_reduction *red, upir_loop_h *out) {
+  if (!c) return UPIR_EINVAL;
+  if (!loop || !body || !out) return upir_fail(c, UPIR_EINVAL, "loop_parallel: null loop, body or out");
+  *out = nullptr;
+  if (c->capturing) return upir_fail(c, UPIR_ESTATE, "loop_parallel during graph capture");
+  upir_loop_obj *lp = new (std::nothrow) upir_loop_obj();
+  if (!lp) return upir_fail(c, UPIR_ENOMEM, "loop handle");
+  upir_status st = describe_loop(c, loop, sched, body, red, lp);
+  if (st) {
+    delete lp;
+    return st;
+  }
+  const int32_t kind = lp->kind;
+  const bool has_red = lp->has_red;
   lp->part_cap = has_red ? 8192 : 0;
   lp->scratch = (unsigned char *)upir_dalloc(c, scratch_bytes(lp->part_cap));
   if (!lp->scratch) {
@@ -469,7 +489,7 @@ extern "C" upir_status upir_loop_parallel(upir_ctx *c, const upir_loop *loop, co
   }
   if ((kind == UPIR_BODY_MATMUL_BF16 || kind == UPIR_BODY_MATMUL_SPLIT3) &&
       !((const upir_matmul_args *)body->args)->workspace) {
-    lp->ws_bytes = upir_matmul_workspace_bytes(kind, M, N, K);
+    lp->ws_bytes = upir_matmul_workspace_bytes(kind, lp->cnt[0], lp->cnt[1], ((const upir_matmul_args *)body->args)->K);
     lp->ws = upir_dalloc(c, lp->ws_bytes);
     if (!lp->ws) {
       free_loop(c, lp);

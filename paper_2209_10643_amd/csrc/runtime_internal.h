@@ -124,6 +124,8 @@ struct upir_ctx {
   int64_t fold_cap = 0;                  // partials per buffer
   int fold_flip = 0;
   std::vector<void *> retired;           // outgrown fold buffers and loop scratch (graphs may use them)
+  void *noalloc_scratch = nullptr;       // this device's static scratch (upir_reduce_noalloc)
+  bool no_alloc = false;                 // inside a call that must not allocate (AUTO skips the model)
 };
 
 // helpers shared by the runtime translation units
@@ -132,6 +134,9 @@ upir_status upir_hipfail(upir_ctx *c, hipError_t e, const char *what);
 void *upir_dalloc(upir_ctx *c, size_t bytes);
 void upir_dfree(upir_ctx *c, void *p);
 void upir_model_free(upir_ctx *c);
+// Validate a loop description and fill *lp from it (no allocation).
+upir_status describe_loop(upir_ctx *c, const upir_loop *loop, const upir_sched *sched, const upir_body *body,
+                          const upir_reduction *red, upir_loop_obj *lp);
 // Device address of [host, host + bytes) inside one mapping (bytes = 0: to
 // the mapping's end, returned in *bytes).
 upir_status upir_map_range(upir_ctx *c, const void *host, size_t *bytes, void **dev);
@@ -160,4 +165,7 @@ void candidate_features(upir_ctx *c, const upir_loop_obj *lp, const upir_spmd &s
                         float f[32]);
 bool model_pick(upir_ctx *c, upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc);
 void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc);
+// Address of the current device's static scratch array (looked up once per
+// device; the device must be current).
+hipError_t noalloc_setup(int device, void **out);
 }  // namespace upir

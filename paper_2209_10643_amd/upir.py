@@ -133,6 +133,8 @@ _SIGS = {
     "upir_reduce_wait": (None, [_ctx_p, C.c_void_p]),
     "upir_reduce": (None, [_ctx_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, P(upir_spmd), P(upir_sched),
                            P(upir_reduction)]),
+    "upir_reduce_noalloc": (None, [_ctx_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, P(upir_spmd),
+                                   P(upir_sched), P(upir_reduction)]),
     "upir_loop_resolve": (None, [_ctx_p, P(upir_spmd), C.c_void_p, P(upir_spmd), P(upir_sched), P(C.c_int32)]),
     "upir_matmul_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int64, C.c_int64, C.c_int64]),
     "upir_graph_begin": (None, [_ctx_p]),
