@@ -6,8 +6,10 @@
 One step = one pass of the headline workload: a 4096 x 4096 float32 Jacobi
 5-point stencil, 100 sweeps, each sweep a collapse(2) worksharing loop with a
 fused float64 max-residual reduction, the 100 sweeps replayed as one HIP
-graph with the grids resident in HBM. ``value`` = algorithmic HBM bytes of a
-step (per sweep: read the 4096^2 grid once, write the interior once) / time.
+graph with the grids already in device memory (two 64 MiB grids: they stay
+resident in the 256 MB last-level cache, the MALL, between sweeps).
+``value`` = algorithmic bytes of a step (per sweep: read the 4096^2 grid
+once, write the interior once) / time.
 
 The same JSON line carries the other workloads as extras: AXPY + sum at
 n = 2^20, the 4096^3 matmul in three precisions, the 2048-task batched graph

@@ -12,8 +12,10 @@
 //  * fast kernels that own the same iterations with wide, coalesced access:
 //    k_stream4 (1-D, chunk 4: one f32x4 per chunk, chunks dealt over the
 //    flat unit id -- the classic grid-stride loop), k_jacobi_tile (tiles of
-//    TH x 256 points staged with their halo in LDS), k_matvec (one 64-lane
-//    wavefront per row).
+//    TH x 256 points; each wavefront streams a strip of rows through
+//    registers, west / east neighbours from adjacent lanes, no LDS),
+//    k_filter7_tile (the same strips for the 7 x 7 filter), k_matvec (one
+//    64-lane wavefront per row).
 // All kernels fuse their reduction (lane -> wavefront -> LDS -> last
 // workgroup combines in float64 in workgroup order).
 #include "upir_launch.h"

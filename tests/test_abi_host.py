@@ -340,3 +340,36 @@ def test_update_task_graph_and_validation(hctx):
     assert [_preds(h, j) for j in range(3)] == want == [[], [0], [1]]
     assert _status("upir_task_update", h, 0x5000, 64, 9, None, 0, C.byref(tid)) == U.UPIR_EINVAL
     assert _status("upir_task_update", h, None, 64, U.UPIR_TO_DEVICE, None, 0, C.byref(tid)) == U.UPIR_EINVAL
+
+
+# Every structure of the C ABI: the C compiler's size and field offsets for
+# the header's declaration must equal the ctypes mirror's.
+ABI_STRUCTS = ["upir_spmd", "upir_dim", "upir_loop", "upir_sched", "upir_reduction", "upir_axpy_args",
+               "upir_sum_args", "upir_jacobi5_args", "upir_matmul_args", "upir_matvec_args", "upir_owner_args",
+               "upir_cover_args", "upir_filter7_args", "upir_body", "upir_depend", "upir_task_trace"]
+C_FIELD_NAMES = {"async_": "async"}  # a Python keyword renamed in the binding
+
+
+def test_struct_layouts_match_header(tmp_path):
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "upir.h"', "int main(void) {"]
+    for s in ABI_STRUCTS:
+        cls = getattr(U, s)
+        lines.append(f'  printf("{s} size %zu\\n", sizeof({s}));')
+        for name, _ in cls._fields_:
+            cname = C_FIELD_NAMES.get(name, name)
+            lines.append(f'  printf("{s} {name} %zu\\n", offsetof({s}, {cname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        s, field, v = ln.split()
+        got[(s, field)] = int(v)
+    for s in ABI_STRUCTS:
+        cls = getattr(U, s)
+        assert got[(s, "size")] == C.sizeof(cls), s
+        for name, _ in cls._fields_:
+            assert got[(s, name)] == getattr(cls, name).offset, (s, name)
