@@ -357,6 +357,39 @@ upir_status upir_tune_db_load(upir_ctx *ctx, const char *path);
 upir_status upir_tune_db_size(upir_ctx *ctx, int64_t *rows);
 upir_status upir_tune_db_row(upir_ctx *ctx, int64_t row, float *feat32, float *log2_us, int64_t *loop_key);
 
+/* Engine schedule of the batched executor (taskwait BATCHED): the tile
+ * (work item) of every task whose schedule is AUTO with no tile of its own,
+ * per body: elements per tile for AXPY and COVER tasks, for SUM tasks, and
+ * rows per tile for MATVEC tasks. A task graph resolves it, in order, to
+ * the schedule the caller set, the exhaustive batch tuner's best for a graph
+ * of the same shape, the cost model's choice, or the default
+ * {16384, 16384, 64}. The candidates are the 27 combinations of AXPY
+ * {8192, 16384, 32768}, SUM {16384, 32768, 65536} and MATVEC {32, 64, 128};
+ * candidate 0 is the default. */
+typedef struct { int64_t tile_axpy, tile_sum, rows_matvec; } upir_engine_sched;
+#define UPIR_ENGINE_CANDIDATES     27
+#define UPIR_ENGINE_FROM_DEFAULT   0
+#define UPIR_ENGINE_FROM_TUNER     1
+#define UPIR_ENGINE_FROM_MODEL     2
+#define UPIR_ENGINE_FROM_CALLER    3
+/* Fix the engine schedule (NULL: back to automatic resolution). Tiles must
+ * be >= 1 and <= 2^24 (UPIR_EINVAL otherwise). */
+upir_status upir_engine_sched_set(upir_ctx *ctx, const upir_engine_sched *sched);
+/* The engine schedule the pending tasks would run with, and its source
+ * (UPIR_ENGINE_FROM_*). May run the cost model (a forward pass on the GPU). */
+upir_status upir_engine_sched_resolve(upir_ctx *ctx, upir_engine_sched *out, int32_t *source);
+/* Candidate idx of the engine schedule and the 32 features of (pending task
+ * graph, candidate) the cost model sees (feat32 may be NULL). */
+upir_status upir_engine_candidate(upir_ctx *ctx, int32_t idx, upir_engine_sched *out, float *feat32);
+/* Exhaustive batch tuner: run the pending task graph with the batched
+ * executor once per candidate and then `reps` times between HIP events,
+ * record one timing-table row per candidate (median time), and remember the
+ * fastest for graphs of this shape. The tasks stay pending. The runs execute
+ * the tasks: a task that updates its data in place (AXPY) is applied
+ * (reps + 1) x 27 times, so callers restore such data before the taskwait
+ * that counts. UPIR_ESTATE during capture or with no pending tasks. */
+upir_status upir_tune_batched(upir_ctx *ctx, int32_t reps, upir_engine_sched *best, double *best_us);
+
 /* Cost model: MLP 32 -> 64 -> 64 -> 1 (float32), trained on the GPU by
  * the library's own forward / backward / Adam kernels. */
 #define UPIR_MLP_PARAMS 6337
@@ -374,7 +407,8 @@ upir_status upir_model_step(upir_ctx *ctx, const float *dev_x, const float *dev_
  * train / holdout mean squared errors. */
 upir_status upir_model_train(upir_ctx *ctx, int32_t epochs, int32_t batch, float lr, int32_t holdout_mod,
                              float *train_mse, float *holdout_mse);
-/* Let AUTO use the model for loops the tuner has not seen (1) or not (0). */
+/* Let AUTO use the model for loops (and task graphs) the tuner has not seen
+ * (1) or not (0). */
 upir_status upir_model_enable(upir_ctx *ctx, int32_t on);
 upir_status upir_model_save(upir_ctx *ctx, const char *path);
 upir_status upir_model_load(upir_ctx *ctx, const char *path);

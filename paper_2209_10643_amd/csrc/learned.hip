@@ -737,7 +737,179 @@ bool model_pick(upir_ctx *c, upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc) {
   return true;
 }
 
+// ------------------------------------------------ engine schedules (batched)
+std::vector<upir_engine_sched> engine_candidates() {
+  std::vector<upir_engine_sched> v;
+  v.push_back(upir_engine_sched{16384, 16384, 64});  // the default first
+  for (int64_t a : {8192, 16384, 32768})
+    for (int64_t s : {16384, 32768, 65536})
+      for (int64_t m : {32, 64, 128})
+        if (!(a == 16384 && s == 16384 && m == 64)) v.push_back(upir_engine_sched{a, s, m});
+  return v;
+}
+
+namespace {
+// engine class of a task: 0 AXPY / COVER, 1 SUM, 2 MATVEC
+int engine_class(int32_t kind) { return kind == UPIR_BODY_SUM ? 1 : (kind == UPIR_BODY_MATVEC ? 2 : 0); }
+
+int64_t task_len(const TaskRec &t) { return t.hi >= 0 ? t.hi - t.lo : t.loop->n; }
+
+double task_bytes(const TaskRec &t) {
+  const double n = (double)task_len(t);
+  switch (t.loop->kind) {
+    case UPIR_BODY_AXPY: return 12.0 * n;
+    case UPIR_BODY_SUM: return 4.0 * n;
+    case UPIR_BODY_MATVEC: return (4.0 * (double)((const upir_matvec_args *)t.loop->args)->cols + 4.0) * n;
+    default: return 8.0 * n;
+  }
+}
+
+// tile a candidate gives a task of class k (engine work items count rows for MATVEC)
+int64_t class_tile(const upir_engine_sched &es, int k) {
+  return k == 0 ? es.tile_axpy : (k == 1 ? es.tile_sum : es.rows_matvec);
+}
+}  // namespace
+
+uint64_t batch_key(const upir_ctx *c) {
+  // FNV-1a over the task count, each task's body and length, the edge count
+  uint64_t h = 1469598103934665603ULL;
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xff;
+      h *= 1099511628211ULL;
+    }
+  };
+  mix(0xBA7C4ULL);
+  mix((uint64_t)c->tasks.size());
+  uint64_t edges = 0;
+  for (const TaskRec &t : c->tasks) {
+    mix((uint64_t)(t.loop ? t.loop->kind : 0));
+    mix((uint64_t)(t.loop ? task_len(t) : 0));
+    edges += t.preds.size();
+  }
+  mix(edges);
+  return h;
+}
+
+// 32 features of (pending task graph, engine candidate). Slot 30 marks a
+// graph row (loop rows leave it 0).
+void batch_features(const upir_ctx *c, const upir_engine_sched &es, float f[32]) {
+  for (int i = 0; i < 32; ++i) f[i] = 0.0f;
+  const size_t n = c->tasks.size();
+  double cnt[3] = {0, 0, 0}, bytes[3] = {0, 0, 0}, items[3] = {0, 0, 0}, lgsum = 0, lgmax = 0, edges = 0;
+  std::vector<int32_t> depth(n, 0);
+  int32_t dmax = 0;
+  for (size_t j = 0; j < n; ++j) {
+    const TaskRec &t = c->tasks[j];
+    if (!t.loop) continue;
+    const int k = engine_class(t.loop->kind);
+    const int64_t len = std::max<int64_t>(task_len(t), 1);
+    cnt[k] += 1;
+    bytes[k] += task_bytes(t);
+    const int64_t tile = std::max<int64_t>(1, class_tile(es, k));
+    items[k] += (double)((len + tile - 1) / tile);
+    lgsum += lg((double)len);
+    lgmax = std::max(lgmax, lg((double)len));
+    edges += (double)t.preds.size();
+    int32_t d = 0;
+    for (int64_t p : t.preds) d = std::max(d, depth[(size_t)p]);
+    depth[j] = d + 1;
+    dmax = std::max(dmax, depth[j]);
+  }
+  const double N = std::max<double>(1.0, (double)n), B = std::max(1.0, bytes[0] + bytes[1] + bytes[2]);
+  const double I = std::max(1.0, items[0] + items[1] + items[2]), grid = 4.0 * c->num_cus;
+  for (int k = 0; k < 3; ++k) {
+    f[k] = (float)(cnt[k] / N);
+    f[3 + k] = (float)(bytes[k] / B);
+    f[12 + k] = (float)(lg((double)class_tile(es, k)) / 24);
+    f[15 + k] = (float)(lg(items[k] + 1) / 24);
+    f[20 + k] = (float)(lg(items[k] > 0 ? bytes[k] / items[k] : 1.0) / 32);
+  }
+  f[6] = (float)(lg(N) / 16);
+  f[7] = (float)(lg(B) / 40);
+  f[8] = (float)(lgsum / N / 32);
+  f[9] = (float)(lgmax / 32);
+  f[10] = (float)(edges / N / 8);
+  f[11] = (float)(dmax / 64.0);
+  f[18] = (float)(lg(I) / 24);
+  f[19] = (float)(lg(I / grid) / 16);
+  f[23] = (float)(lg(grid) / 16);
+  f[30] = 1.0f;
+}
+
+bool model_pick_engine(upir_ctx *c, upir_engine_sched &es) {
+  if (!c->model || !c->model_on || c->capturing || c->no_alloc || c->tasks.empty()) return false;
+  const auto cs = engine_candidates();
+  std::vector<float> X(cs.size() * 32), y(cs.size());
+  for (size_t i = 0; i < cs.size(); ++i) batch_features(c, cs[i], &X[i * 32]);
+  float *dX = (float *)upir_dalloc(c, X.size() * 4), *dY = (float *)upir_dalloc(c, cs.size() * 4);
+  bool ok = dX && dY;
+  if (ok) ok = hipMemcpyAsync(dX, X.data(), X.size() * 4, hipMemcpyHostToDevice, c->stream) == hipSuccess;
+  if (ok) ok = fwd_launch(c, dX, (int64_t)cs.size(), dY, nullptr, nullptr) == hipSuccess;
+  if (ok) ok = hipMemcpyAsync(y.data(), dY, y.size() * 4, hipMemcpyDeviceToHost, c->stream) == hipSuccess;
+  if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
+  upir_dfree(c, dX);
+  upir_dfree(c, dY);
+  if (!ok) return false;
+  size_t b = 0;
+  for (size_t i = 1; i < y.size(); ++i)
+    if (y[i] < y[b]) b = i;
+  es = cs[b];
+  return true;
+}
+
+upir_status resolve_engine_sched(upir_ctx *c, upir_engine_sched &es, int32_t &source) {
+  if (c->engine_set) {
+    es = c->engine_sched;
+    source = UPIR_ENGINE_FROM_CALLER;
+    return UPIR_OK;
+  }
+  auto it = c->tuned_engine.find(batch_key(c));
+  if (it != c->tuned_engine.end()) {
+    es = it->second.first;
+    source = UPIR_ENGINE_FROM_TUNER;
+    return UPIR_OK;
+  }
+  if (model_pick_engine(c, es)) {
+    source = UPIR_ENGINE_FROM_MODEL;
+    return UPIR_OK;
+  }
+  es = engine_candidates()[0];
+  source = UPIR_ENGINE_FROM_DEFAULT;
+  return UPIR_OK;
+}
+
 }  // namespace upir
+
+extern "C" upir_status upir_engine_sched_set(upir_ctx *c, const upir_engine_sched *es) {
+  if (!c) return UPIR_EINVAL;
+  if (!es) {
+    c->engine_set = false;
+    return UPIR_OK;
+  }
+  for (int64_t t : {es->tile_axpy, es->tile_sum, es->rows_matvec})
+    if (t < 1 || t > (1 << 24)) return upir_fail(c, UPIR_EINVAL, "engine tile %lld", (long long)t);
+  c->engine_sched = *es;
+  c->engine_set = true;
+  return UPIR_OK;
+}
+
+extern "C" upir_status upir_engine_sched_resolve(upir_ctx *c, upir_engine_sched *out, int32_t *source) {
+  if (!c || !out) return UPIR_EINVAL;
+  int32_t src = 0;
+  upir_status st = resolve_engine_sched(c, *out, src);
+  if (source) *source = src;
+  return st;
+}
+
+extern "C" upir_status upir_engine_candidate(upir_ctx *c, int32_t idx, upir_engine_sched *out, float *feat) {
+  if (!c || !out) return UPIR_EINVAL;
+  const auto cs = engine_candidates();
+  if (idx < 0 || idx >= (int)cs.size()) return upir_fail(c, UPIR_EINVAL, "engine candidate %d of %zu", idx, cs.size());
+  *out = cs[idx];
+  if (feat) batch_features(c, cs[idx], feat);
+  return UPIR_OK;
+}
 
 // ------------------------------------------------------------------- tuner
 extern "C" upir_status upir_candidates(upir_ctx *c, upir_loop_h lp, int32_t *count) {

@@ -124,6 +124,9 @@ struct upir_ctx {
   int64_t fold_cap = 0;                  // partials per buffer
   int fold_flip = 0;
   std::vector<void *> retired;           // outgrown fold buffers and loop scratch (graphs may use them)
+  bool engine_set = false;               // the caller fixed the engine schedule
+  upir_engine_sched engine_sched{};      // ... to this
+  std::unordered_map<uint64_t, std::pair<upir_engine_sched, double>> tuned_engine;  // batch key -> best, us
   void *noalloc_scratch = nullptr;       // this device's static scratch (upir_reduce_noalloc)
   bool no_alloc = false;                 // inside a call that must not allocate (AUTO skips the model)
 };
@@ -165,6 +168,15 @@ void candidate_features(upir_ctx *c, const upir_loop_obj *lp, const upir_spmd &s
                         float f[32]);
 bool model_pick(upir_ctx *c, upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc);
 void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sched &sc);
+// Engine schedules of the batched executor: candidates (0 = default), the
+// shape key of the pending task graph, features of (graph, candidate), and
+// the cost model's pick among the candidates (false when the model is off).
+std::vector<upir_engine_sched> engine_candidates();
+uint64_t batch_key(const upir_ctx *c);
+void batch_features(const upir_ctx *c, const upir_engine_sched &es, float f[32]);
+bool model_pick_engine(upir_ctx *c, upir_engine_sched &es);
+// Engine schedule of the pending graph and its source (UPIR_ENGINE_FROM_*).
+upir_status resolve_engine_sched(upir_ctx *c, upir_engine_sched &es, int32_t &source);
 // Address of the current device's static scratch array (looked up once per
 // device; the device must be current).
 hipError_t noalloc_setup(int device, void **out);

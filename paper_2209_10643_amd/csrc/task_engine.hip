@@ -42,8 +42,12 @@ struct EngineD {
   const TaskD *tasks;
   int32_t ntasks, total_tiles, init_tiles, pad_;
   const int32_t *succ, *pred, *init_work, *init_base, *indeg0;
-  int32_t *indeg, *tiles_done, *task_base, *work;
-  int32_t *ctrl;  // [0] next work item [1] work items reserved [2] error
+  int32_t *indeg, *tiles_done, *task_base;
+  unsigned long long *work;  // per item: (tile << 32) | (task + 1); 0 until pushed
+  int32_t *ctrl;  // control block: [0] work items reserved, [1] error; queue q's claim
+                  // counter at int index (q + 1) * ENGINE_CTRL_LINE / 4
+  int32_t nq;     // work queues in use (<= ENGINE_QUEUES, <= grid)
+  int32_t pad2_;
   unsigned long long *clock;
   double *partials;
   uint64_t *tok, *tstart, *tdone;
@@ -62,6 +66,15 @@ __device__ inline int ld_i(int32_t *p) { return __hip_atomic_load(p, __ATOMIC_RE
 __device__ inline void st_i(int32_t *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ inline int add_i(int32_t *p, int v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long ld_u64(unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_u64(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long work_item(int task, int tile) {
+  return ((unsigned long long)(unsigned)tile << 32) | (unsigned)(task + 1);
 }
 __device__ inline unsigned long long tick(unsigned long long *p) {
   return __hip_atomic_fetch_add(p, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -123,11 +136,18 @@ __global__ void k_engine_reset(EngineD E) {
     st_i(&E.tiles_done[i], 0);
     st_i(&E.task_base[i], E.init_base[i]);
   }
-  for (int w = i0; w < E.total_tiles; w += st) st_i(&E.work[w], w < E.init_tiles ? E.init_work[w] + 1 : 0);
+  for (int w = i0; w < E.total_tiles; w += st) {
+    unsigned long long v = 0;
+    if (w < E.init_tiles) {
+      const int task = E.init_work[w];
+      v = work_item(task, w - E.init_base[task]);
+    }
+    st_u64(&E.work[w], v);
+  }
   if (i0 == 0) {
-    st_i(&E.ctrl[0], 0);
-    st_i(&E.ctrl[1], E.init_tiles);
-    st_i(&E.ctrl[2], 0);
+    st_i(&E.ctrl[0], E.init_tiles);
+    st_i(&E.ctrl[1], 0);
+    for (int q = 0; q < ENGINE_QUEUES; ++q) st_i(&E.ctrl[(q + 1) * (ENGINE_CTRL_LINE / 4)], 0);
     __hip_atomic_store(E.clock, 0ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -320,20 +340,30 @@ __global__ void __launch_bounds__(256) k_engine(EngineD E) {
   __shared__ int s_task, s_tile, s_last;
   __shared__ float s_red[16];
   __shared__ double s_red64[16];
-  int32_t *next = &E.ctrl[0], *reserved = &E.ctrl[1], *err = &E.ctrl[2];
+  // Work items are dealt round-robin over nq queues, each with its own claim
+  // counter (one atomic per claim; a single counter for the whole chip
+  // serialised the claims). Workgroup b claims from queue b mod nq, items
+  // q, q + nq, q + 2 nq, ... in order. Thread 0 claims one item ahead: the
+  // claim for the next item is issued before the current tile runs, so its
+  // round trip overlaps the tile's memory traffic. A workgroup finishes its
+  // current tile before it waits for a claimed item to be pushed, so holding
+  // one claimed item per workgroup cannot stall the graph.
+  const int q = (int)(blockIdx.x % (unsigned)E.nq);
+  int32_t *next = &E.ctrl[(q + 1) * (ENGINE_CTRL_LINE / 4)], *reserved = &E.ctrl[0], *err = &E.ctrl[1];
+  int w = 0;
+  if (threadIdx.x == 0) w = q + E.nq * add_i(next, 1);
   for (;;) {
     if (threadIdx.x == 0) {
       int task = -1, tile = 0;
-      const int w = add_i(next, 1);
       if (w < E.total_tiles) {
         // wait until the push that reserves item w has filled it in
         long long spins = 0;
         int seen = -1;
         for (;;) {
-          const int v = ld_i(&E.work[w]);
-          if (v > 0) {
-            task = v - 1;
-            tile = w - ld_i(&E.task_base[task]);
+          const unsigned long long v = ld_u64(&E.work[w]);
+          if (v != 0) {
+            task = (int)(unsigned)(v & 0xffffffffULL) - 1;
+            tile = (int)(v >> 32);
             if (tile == 0 && E.tstart) E.tstart[task] = tick(E.clock);
             break;
           }
@@ -349,6 +379,7 @@ __global__ void __launch_bounds__(256) k_engine(EngineD E) {
             break;
           }
         }
+        if (task >= 0) w = q + E.nq * add_i(next, 1);
       }
       s_task = task;
       s_tile = tile;
@@ -364,7 +395,11 @@ __global__ void __launch_bounds__(256) k_engine(EngineD E) {
       if (threadIdx.x == 0)
         coh_store((unsigned long long *)&E.partials[d.part_base + k], __builtin_bit_cast(unsigned long long, (double)wg));
     }
-    complete_own_accesses();  // this thread's tile stores have reached the coherent level
+    // Before the tile counts as done: a task whose data another task touches
+    // has every thread's tile stores at the coherent level; otherwise only
+    // the reduction partial (thread 0's store) must have landed: no other
+    // task reads the data, and the kernel's end publishes it.
+    if (d.mem == MEM_COHERENT || (d.red_op && threadIdx.x == 0)) complete_own_accesses();
     __syncthreads();
     if (threadIdx.x == 0) s_last = (add_i(&E.tiles_done[t], 1) == d.ntiles - 1);
     __syncthreads();
@@ -392,9 +427,7 @@ __global__ void __launch_bounds__(256) k_engine(EngineD E) {
           if (add_i(&E.indeg[s], -1) == 1) {
             const int nt = E.tasks[s].ntiles;
             const int base = add_i(reserved, nt);
-            st_i(&E.task_base[s], base);
-            complete_own_accesses();
-            for (int q = 0; q < nt; ++q) st_i(&E.work[base + q], s + 1);
+            for (int q = 0; q < nt; ++q) st_u64(&E.work[base + q], work_item(s, q));
           }
         }
       }
@@ -422,14 +455,17 @@ __global__ void k_zero_u64(unsigned long long *p) { *p = 0ULL; }
 
 using namespace upir;
 
-// 16384 elements (64 KiB of each array) or 64 matvec rows: enough work per tile to
-// stream, small enough that the tiles of a long task spread over the chip
-static int64_t default_task_tile(int32_t kind) { return kind == UPIR_BODY_MATVEC ? 64 : 16384; }
-
-// tile size of a task: the schedule's tile[0] if given, else the default
-static int64_t task_tile(upir_ctx *, upir_loop_obj *lp) {
+// Tile of a task in the engine: the task's own schedule tile if it gives
+// one; for an AUTO schedule the graph's engine schedule (per body); else the
+// default (16384 elements, 64 KiB of each array, or 64 MATVEC rows).
+static int64_t task_tile(upir_loop_obj *lp, const upir_engine_sched &es) {
   if (lp->sched.tile[0] > 0) return lp->sched.tile[0];
-  return default_task_tile(lp->kind);
+  const upir_engine_sched &use = lp->sched.policy == UPIR_SCHED_AUTO ? es : engine_candidates()[0];
+  switch (lp->kind) {
+    case UPIR_BODY_MATVEC: return use.rows_matvec;
+    case UPIR_BODY_SUM: return use.tile_sum;
+    default: return use.tile_axpy;
+  }
 }
 
 // Per-context device clock for the plain executor's trace stamps.
@@ -489,19 +525,17 @@ upir_status upir_plain_trace(upir_ctx *c, int64_t task, const int32_t *preds, in
   return UPIR_OK;
 }
 
-upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **gout) {
+// The engine's device state for the pending tasks under one engine
+// schedule: one allocation (tables, then mutable state) and the launch shape.
+struct EnginePrep {
+  unsigned char *dev = nullptr;
+  EngineD E{};
+  int grid = 0, rgrid = 0;
+  int64_t total_tiles = 0;
+};
+
+static upir_status engine_prepare(upir_ctx *c, const upir_engine_sched &es, EnginePrep &P) {
   const int32_t n = (int32_t)c->tasks.size();
-  if (n == 0) {
-    if (capture_only) {
-      upir_status st = upir_graph_begin(c);
-      if (st) return st;
-      upir_graph_h g;
-      st = upir_graph_end(c, &g);
-      if (st == UPIR_OK) *gout = g;
-      return st;
-    }
-    return UPIR_OK;
-  }
   // ---- host tables (task_graph.cpp builds and lays them out)
   std::vector<TaskD> td(n);
   std::vector<std::vector<int64_t>> preds(n);
@@ -522,7 +556,7 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
       d.lb += c->tasks[j].lo * d.step;
       d.n = c->tasks[j].hi - c->tasks[j].lo;
     }
-    d.tile = task_tile(c, lp);
+    d.tile = task_tile(lp, es);
     if (lp->has_red) {
       d.init = lp->red.init;
       d.result = (double *)(lp->red.result_on_host ? (void *)(lp->scratch + SCR_RESULT) : lp->red.result);
@@ -561,11 +595,13 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
   const int64_t total_tiles = lay.total_tiles;
   // ---- device buffer: the static image, then mutable state
   unsigned char *dev = (unsigned char *)upir_dalloc(c, lay.total_bytes);
+  P.dev = dev;
   if (!dev) return upir_fail(c, UPIR_ENOMEM, "task engine tables (%zu bytes)", lay.total_bytes);
   hipError_t e = hipMemcpyAsync(dev, host.data(), lay.static_bytes, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     upir_dfree(c, dev);
+    P.dev = nullptr;
     return upir_hipfail(c, e, "task table copy");
   }
   EngineD E{};
@@ -578,9 +614,10 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
   E.indeg = (int32_t *)(dev + lay.indeg);
   E.tiles_done = (int32_t *)(dev + lay.tiles_done);
   E.task_base = (int32_t *)(dev + lay.task_base);
-  E.work = (int32_t *)(dev + lay.work);
+  E.work = (unsigned long long *)(dev + lay.work);
   E.ctrl = (int32_t *)(dev + lay.ctrl);
   E.clock = (unsigned long long *)(dev + lay.ctrl + 16);
+  static_assert(ENGINE_CTRL_LINE >= 24, "control line holds the counters and the clock");
   E.partials = (double *)(dev + lay.partials);
   E.ntasks = n;
   E.total_tiles = (int32_t)total_tiles;
@@ -592,19 +629,58 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
   const char *gs = getenv("UPIR_ENGINE_GRID");
   int grid = c->num_cus * 4;
   if (gs && atoi(gs) > 0) grid = atoi(gs);
+  E.nq = std::min(grid, ENGINE_QUEUES);
   const int rgrid = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (std::max<int64_t>(n, total_tiles) + 255) / 256));
-  upir_status st = UPIR_OK;
+  P.E = E;
+  P.grid = grid;
+  P.rgrid = rgrid;
+  P.total_tiles = total_tiles;
+  return UPIR_OK;
+}
+
+static void engine_launch(upir_ctx *c, const EnginePrep &P) {
+  hipLaunchKernelGGL(k_engine_reset, dim3(P.rgrid), dim3(256), 0, c->stream, P.E);
+  hipLaunchKernelGGL(k_engine, dim3(P.grid), dim3(256), 0, c->stream, P.E);
+}
+
+// Wait for the engine and read its error flag.
+static upir_status engine_check(upir_ctx *c, const EnginePrep &P) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  int32_t ctrl[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpy(ctrl, P.E.ctrl, sizeof ctrl, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return upir_hipfail(c, e, "task engine");
+  if (ctrl[1]) return upir_fail(c, UPIR_EDEPEND, "task graph did not drain (%d of %d work items reserved)", ctrl[0], (int)P.total_tiles);
+  return UPIR_OK;
+}
+
+upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **gout) {
+  const int32_t n = (int32_t)c->tasks.size();
+  if (n == 0) {
+    if (capture_only) {
+      upir_status st = upir_graph_begin(c);
+      if (st) return st;
+      upir_graph_h g;
+      st = upir_graph_end(c, &g);
+      if (st == UPIR_OK) *gout = g;
+      return st;
+    }
+    return UPIR_OK;
+  }
+  upir_engine_sched es{};
+  int32_t src = 0;
+  upir_status st = resolve_engine_sched(c, es, src);  // before any capture: the model may run
+  if (st) return st;
+  EnginePrep P;
+  st = engine_prepare(c, es, P);
+  if (st) return st;
   if (capture_only) {
     st = upir_graph_begin(c);
     if (st) {
-      upir_dfree(c, dev);
+      upir_dfree(c, P.dev);
       return st;
     }
-  }
-  hipLaunchKernelGGL(k_engine_reset, dim3(rgrid), dim3(256), 0, c->stream, E);
-  hipLaunchKernelGGL(k_engine, dim3(grid), dim3(256), 0, c->stream, E);
-  e = hipGetLastError();
-  if (capture_only) {
+    engine_launch(c, P);
+    const hipError_t e = hipGetLastError();
     upir_graph_h g = nullptr;
     st = upir_graph_end(c, &g);
     if (e != hipSuccess && st == UPIR_OK) {
@@ -612,18 +688,80 @@ upir_status upir_batched_run(upir_ctx *c, bool capture_only, upir_graph_obj **go
       st = upir_hipfail(c, e, "task engine launch");
     }
     if (st == UPIR_OK) {
-      g->owned.push_back(dev);
+      g->owned.push_back(P.dev);
       *gout = g;
     } else {
-      upir_dfree(c, dev);
+      upir_dfree(c, P.dev);
     }
     return st;
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  int32_t ctrl[3] = {0, 0, 0};
-  if (e == hipSuccess) e = hipMemcpy(ctrl, E.ctrl, sizeof ctrl, hipMemcpyDeviceToHost);
-  upir_dfree(c, dev);
-  if (e != hipSuccess) return upir_hipfail(c, e, "task engine");
-  if (ctrl[2]) return upir_fail(c, UPIR_EDEPEND, "task graph did not drain (claimed %d, reserved %d of %d work items)", ctrl[0], ctrl[1], (int)total_tiles);
+  engine_launch(c, P);
+  const hipError_t e = hipGetLastError();
+  st = e != hipSuccess ? upir_hipfail(c, e, "task engine launch") : engine_check(c, P);
+  if (st) (void)hipStreamSynchronize(c->stream);
+  upir_dfree(c, P.dev);
+  return st;
+}
+
+extern "C" upir_status upir_tune_batched(upir_ctx *c, int32_t reps, upir_engine_sched *best, double *best_us) {
+  if (!c) return UPIR_EINVAL;
+  if (c->none) return upir_fail(c, UPIR_ESTATE, "host-only context");
+  if (c->capturing) return upir_fail(c, UPIR_ESTATE, "tuning during graph capture");
+  if (c->tasks.empty()) return upir_fail(c, UPIR_ESTATE, "no pending tasks to tune");
+  if (reps < 1 || reps > 1000) return upir_fail(c, UPIR_EINVAL, "reps");
+  for (const TaskRec &t : c->tasks)
+    if (!t.loop) return upir_fail(c, UPIR_EUNSUPPORTED, "data_update tasks run with taskwait PLAIN");
+  upir_status st = settle(c);
+  if (st) return st;
+  const auto cs = engine_candidates();
+  const uint64_t key = batch_key(c);
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return upir_fail(c, UPIR_EHIP, "event create");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return upir_fail(c, UPIR_EHIP, "event create");
+  }
+  double bus = 1e300;
+  int bi = -1;
+  std::vector<TuneRow> rows;
+  for (size_t i = 0; i < cs.size() && st == UPIR_OK; ++i) {
+    EnginePrep P;
+    st = engine_prepare(c, cs[i], P);
+    if (st) break;
+    engine_launch(c, P);  // warm-up
+    st = engine_check(c, P);
+    std::vector<float> ms;
+    for (int r = 0; r < reps && st == UPIR_OK; ++r) {
+      float t = 0;
+      if (hipEventRecord(a, c->stream) != hipSuccess) st = upir_fail(c, UPIR_EHIP, "event record");
+      if (st == UPIR_OK) engine_launch(c, P);
+      if (st == UPIR_OK && (hipEventRecord(b, c->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                            hipEventElapsedTime(&t, a, b) != hipSuccess))
+        st = upir_fail(c, UPIR_EHIP, "event wait");
+      if (st == UPIR_OK) st = engine_check(c, P);
+      ms.push_back(t);
+    }
+    (void)hipStreamSynchronize(c->stream);
+    upir_dfree(c, P.dev);
+    if (st) break;
+    std::sort(ms.begin(), ms.end());
+    const double us = 1e3 * ms[ms.size() / 2];
+    TuneRow row{};
+    batch_features(c, cs[i], row.feat);
+    row.log2_us = (float)log2(std::max(us, 1e-3));
+    row.loop_key = (int64_t)(key & 0x7FFFFFFFFFFFFFFFULL);
+    rows.push_back(row);
+    if (us < bus) {
+      bus = us;
+      bi = (int)i;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st) return st;
+  c->db.insert(c->db.end(), rows.begin(), rows.end());
+  c->tuned_engine[key] = std::make_pair(cs[bi], bus);
+  if (best) *best = cs[bi];
+  if (best_us) *best_us = bus;
   return UPIR_OK;
 }

@@ -249,10 +249,10 @@ bool build_engine_tables(std::vector<TaskD> &td, const std::vector<std::vector<i
   o += align256(4 * n + 4);
   L.task_base = o;
   o += align256(4 * n + 4);
-  L.work = o;
-  o += align256(4 * (size_t)total_tiles + 4);
-  L.ctrl = o;
-  o += align256(64);
+  L.work = o;  // one 64-bit item per tile: (tile index << 32) | (task + 1); 0 = not yet pushed
+  o += align256(8 * (size_t)total_tiles + 8);
+  L.ctrl = o;  // counters, each on its own 128-byte line (see ENGINE_CTRL_BYTES)
+  o += align256(ENGINE_CTRL_BYTES);
   L.partials = o;
   o += align256(8 * (size_t)std::max<int64_t>(parts, 1));
   L.total_bytes = o;

@@ -69,12 +69,20 @@ struct TaskD {
   int32_t pad_;
 };
 
+// The engine's control block: line 0 holds the reserved-items counter
+// (int32 at byte 0), the error flag (byte 4) and the stamp clock (uint64 at
+// byte 16); line 1 + q holds the claim counter of work queue q (work items
+// q, q + Q, q + 2Q, ... for Q queues), one 128-byte line each.
+constexpr int ENGINE_QUEUES = 8;
+constexpr size_t ENGINE_CTRL_LINE = 128;
+constexpr size_t ENGINE_CTRL_BYTES = ENGINE_CTRL_LINE * (1 + ENGINE_QUEUES);
+
 // Byte offsets of the engine's sections in its one device allocation (each
 // 256-byte aligned). [0, static_bytes) is the image built on the host;
 // the rest is mutable state the reset kernel initialises.
 struct EngineLayout {
   size_t tasks, succ, pred, init_work, init_base, indeg0;  // static
-  size_t indeg, tiles_done, task_base, work, ctrl, partials;  // mutable
+  size_t indeg, tiles_done, task_base, work, ctrl, partials;  // mutable; work: 8 bytes per tile
   size_t static_bytes, total_bytes;
   int32_t ntasks, total_tiles, init_tiles;
   int64_t edges, parts;

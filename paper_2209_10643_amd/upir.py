@@ -32,6 +32,8 @@ UPIR_DT_F32, UPIR_DT_F64, UPIR_DT_I32, UPIR_DT_I64 = 1, 2, 3, 4
 UPIR_DEP_IN, UPIR_DEP_OUT, UPIR_DEP_INOUT = 1, 2, 3
 UPIR_TASKWAIT_PLAIN, UPIR_TASKWAIT_BATCHED = 0, 1
 UPIR_MLP_PARAMS = 6337
+UPIR_ENGINE_CANDIDATES = 27
+(UPIR_ENGINE_FROM_DEFAULT, UPIR_ENGINE_FROM_TUNER, UPIR_ENGINE_FROM_MODEL, UPIR_ENGINE_FROM_CALLER) = range(4)
 VARIANTS = {0: "generic", 1: "stream4", 2: "jacobi_tile", 3: "matvec_wave", 4: "matmul_mfma", 5: "dynamic",
             6: "filter7_tile"}
 
@@ -106,6 +108,10 @@ class upir_task_trace(C.Structure):
     _fields_ = [("tokens", C.c_void_p), ("start_stamp", C.c_void_p), ("done_stamp", C.c_void_p)]
 
 
+class upir_engine_sched(C.Structure):
+    _fields_ = [("tile_axpy", C.c_int64), ("tile_sum", C.c_int64), ("rows_matvec", C.c_int64)]
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 P = C.POINTER
@@ -159,6 +165,10 @@ _SIGS = {
     "upir_tune_db_load": (None, [_ctx_p, C.c_char_p]),
     "upir_tune_db_size": (None, [_ctx_p, P(C.c_int64)]),
     "upir_tune_db_row": (None, [_ctx_p, C.c_int64, P(C.c_float), P(C.c_float), P(C.c_int64)]),
+    "upir_engine_sched_set": (None, [_ctx_p, P(upir_engine_sched)]),
+    "upir_engine_sched_resolve": (None, [_ctx_p, P(upir_engine_sched), P(C.c_int32)]),
+    "upir_engine_candidate": (None, [_ctx_p, C.c_int32, P(upir_engine_sched), P(C.c_float)]),
+    "upir_tune_batched": (None, [_ctx_p, C.c_int32, P(upir_engine_sched), P(C.c_double)]),
     "upir_model_init": (None, [_ctx_p, C.c_uint64]),
     "upir_model_set_params": (None, [_ctx_p, P(C.c_float)]),
     "upir_model_get_params": (None, [_ctx_p, P(C.c_float)]),

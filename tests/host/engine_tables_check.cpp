@@ -94,6 +94,8 @@ int main(int argc, char **argv) {
   CHECK(img.size() == L.static_bytes, "image size");
   CHECK(L.indeg == L.static_bytes, "mutable part starts after the image");
   CHECK(L.ntasks == n, "ntasks");
+  CHECK(L.ctrl - L.work >= 8 * (size_t)L.total_tiles, "work list holds one 64-bit item per tile");
+  CHECK(L.partials - L.ctrl >= ENGINE_CTRL_BYTES, "control block holds one line per work queue");
 
   // tasks: tiles, partial ranges, CSR ranges
   const TaskD *T = at<TaskD>(img, L.tasks);

@@ -346,7 +346,8 @@ def test_update_task_graph_and_validation(hctx):
 # the header's declaration must equal the ctypes mirror's.
 ABI_STRUCTS = ["upir_spmd", "upir_dim", "upir_loop", "upir_sched", "upir_reduction", "upir_axpy_args",
                "upir_sum_args", "upir_jacobi5_args", "upir_matmul_args", "upir_matvec_args", "upir_owner_args",
-               "upir_cover_args", "upir_filter7_args", "upir_body", "upir_depend", "upir_task_trace"]
+               "upir_cover_args", "upir_filter7_args", "upir_body", "upir_depend", "upir_task_trace",
+               "upir_engine_sched"]
 C_FIELD_NAMES = {"async_": "async"}  # a Python keyword renamed in the binding
 
 
