@@ -554,8 +554,9 @@ def make_batched(torch, ctx, seed=12345, n_tasks=2048, lmin=8, lmax=22, spec=Non
     `spec` = (kinds, lengths, preds) replaces the recipe (training graphs)."""
     kinds, lens, preds = spec if spec is not None else synth.batched_spec(seed, n_tasks, lmin, lmax)
     tasks, bytes_alg = [], 0
+    inputs = synth.batched_inputs_torch_all(seed, kinds, lens, device="cuda")
     for j, (k, L) in enumerate(zip(kinds, lens)):
-        d = synth.batched_inputs_torch(seed, j, k, L, device="cuda")
+        d = inputs[j]
         if k == "axpy":
             d["y0"] = d["y"].clone()
             tasks.append(("axpy", L, d))

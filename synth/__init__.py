@@ -136,6 +136,36 @@ def uniform_01_torch(seed: int, stream: int, n: int, start: int = 0, device="cpu
     return (k.to(torch.float64) * 2.0 ** -24).to(torch.float32)
 
 
+def uniform_pm1_torch_segments(seed: int, streams, lengths, align: int = 64, device="cpu",
+                               chunk: int = 1 << 27):
+    """Many uniform_pm1 sequences in one buffer: segment k holds
+    uniform_pm1(seed, streams[k], lengths[k]) and starts at a multiple of
+    `align` elements (the gap holds the same stream's next values). Returns
+    (buffer, offsets). Generated in a few passes of `chunk` elements, so a
+    whole workload costs tens of kernel launches, not tens per segment."""
+    import torch
+    lengths = np.asarray(lengths, dtype=np.int64)
+    padded = (lengths + align - 1) // align * align
+    offs = np.zeros(len(lengths) + 1, dtype=np.int64)
+    np.cumsum(padded, out=offs[1:])
+    total = int(offs[-1])
+    keys = torch.tensor([_to_i64(_key(seed, int(st))) for st in streams] or [0], dtype=torch.int64, device=device)
+    starts = torch.from_numpy(offs[:-1].copy()).to(device)
+    seg_bounds = torch.from_numpy(offs[1:].copy()).to(device)
+    out = torch.empty(total, dtype=torch.float32, device=device)
+    for c0 in range(0, total, chunk):
+        c1 = min(total, c0 + chunk)
+        g = torch.arange(c0, c1, dtype=torch.int64, device=device)
+        seg = torch.searchsorted(seg_bounds, g, right=True)
+        z = (g - starts[seg] + 1) * _to_i64(GOLDEN) + keys[seg]
+        z = (z ^ _lsr(torch, z, 30)) * _to_i64(_M1)
+        z = (z ^ _lsr(torch, z, 27)) * _to_i64(_M2)
+        z = z ^ _lsr(torch, z, 31)
+        k = _lsr(torch, z, 40)
+        out[c0:c1] = ((k - (1 << 23)).to(torch.float64) * 2.0 ** -23).to(torch.float32)
+    return out, offs
+
+
 # --------------------------------------------------------------------------
 # The batched-task workload: many uneven 1-D loops with random depend edges.
 # Only the recipe of the inputs (kinds, lengths, edges, values) lives here.
@@ -176,6 +206,40 @@ def batched_inputs(seed: int, j: int, kind: str, L: int) -> dict:
         return {"x": uniform_pm1(seed, 10 * j + 1, L)}
     rows = batched_rows(L)
     return {"A": uniform_pm1(seed, 10 * j + 1, rows * 256).reshape(rows, 256), "x": uniform_pm1(seed, 10 * j + 2, 256)}
+
+
+def batched_inputs_torch_all(seed: int, kinds, lens, device="cuda") -> list:
+    """batched_inputs_torch for every task at once: the same values, as
+    views into four buffers (x, y, A and the MATVEC x of all tasks), each
+    task's array starting on a 256-byte boundary. A few dozen kernel
+    launches for the whole workload."""
+    roles = {"x": [], "y": [], "A": [], "v": []}  # (task, stream, length)
+    for j, (kind, L) in enumerate(zip(kinds, lens)):
+        if kind == "axpy":
+            roles["x"].append((j, 10 * j + 1, L))
+            roles["y"].append((j, 10 * j + 2, L))
+        elif kind == "sum":
+            roles["x"].append((j, 10 * j + 1, L))
+        else:
+            rows = batched_rows(L)
+            roles["A"].append((j, 10 * j + 1, rows * 256))
+            roles["v"].append((j, 10 * j + 2, 256))
+    out = [dict() for _ in kinds]
+    for role, items in roles.items():
+        if not items:
+            continue
+        buf, offs = uniform_pm1_torch_segments(seed, [st for _, st, _ in items], [n for _, _, n in items],
+                                               device=device)
+        for k, (j, _, n) in enumerate(items):
+            v = buf[int(offs[k]):int(offs[k]) + n]
+            if role == "A":
+                out[j]["A"] = v.reshape(-1, 256)
+            else:
+                out[j]["x" if role in ("x", "v") else "y"] = v
+    for j, kind in enumerate(kinds):
+        if kind == "axpy":
+            out[j]["a"] = 2.5
+    return out
 
 
 def batched_inputs_torch(seed: int, j: int, kind: str, L: int, device="cuda") -> dict:
