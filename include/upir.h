@@ -276,7 +276,9 @@ upir_status upir_reduce_noalloc(upir_ctx *ctx, int32_t op, int32_t dtype, const 
  * resolution): teams, units and the resolved schedule. */
 upir_status upir_loop_resolve(upir_ctx *ctx, const upir_spmd *spmd, upir_loop_h loop,
                               upir_spmd *spmd_out, upir_sched *sched_out, int32_t *variant_out);
-/* Bytes of BF16 workspace a MATMUL_BF16 / MATMUL_SPLIT3 body needs. */
+/* Bytes of BF16 workspace a MATMUL_BF16 / MATMUL_SPLIT3 body needs:
+ * (M + N) x K' x 2 (x 2 again for the split's low parts), K' = K rounded up
+ * to a multiple of 32. */
 size_t upir_matmul_workspace_bytes(int32_t kind, int64_t M, int64_t N, int64_t K);
 
 /* ------------------------------------------------- graphs (stream replay) */

@@ -17,22 +17,29 @@ __device__ inline uint16_t to_bf16_rne(float x) {
 }
 __device__ inline float bf16f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// Workspace element (row, k) of an operand with `rows` rows: rows of K
+// (layout 0), or k-panels of 32 (layout 1): panel k / 32 holds 32 k of every
+// row, row after row, so the rows x 32 block one k step reads is contiguous.
+__device__ inline int64_t ws_index(int panel, int64_t row, int64_t k, int64_t rows, int64_t K) {
+  return panel ? (((k >> 5) * rows + row) << 5) + (k & 31) : row * K + k;
+}
+
 // A (M x K, lda) -> ah / al (M x K, dense). Row-major, coalesced.
 __global__ void __launch_bounds__(256) k_split_rows(const float *__restrict__ A, int64_t M, int64_t K, int64_t lda,
-                                                    uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+                                                    uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int panel) {
   const int64_t total = M * K;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / K, k = e - i * K;
+    const int64_t i = e / K, k = e - i * K, d = ws_index(panel, i, k, M, K);
     const float x = A[i * lda + k];
     const uint16_t h = to_bf16_rne(x);
-    hi[e] = h;
-    if (lo) lo[e] = to_bf16_rne(x - bf16f(h));
+    hi[d] = h;
+    if (lo) lo[d] = to_bf16_rne(x - bf16f(h));
   }
 }
 
 // B (K x N, ldb) -> bh / bl transposed (N x K, dense) through a 64 x 64 LDS tile.
 __global__ void __launch_bounds__(256) k_split_cols(const float *__restrict__ B, int64_t K, int64_t N, int64_t ldb,
-                                                    uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+                                                    uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int panel) {
   __shared__ float t[64][65];
   const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
   const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;  // 64 x 4
@@ -46,8 +53,9 @@ __global__ void __launch_bounds__(256) k_split_cols(const float *__restrict__ B,
     if (n < N && k < K) {
       const float x = t[tx][r];
       const uint16_t h = to_bf16_rne(x);
-      hi[n * K + k] = h;
-      if (lo) lo[n * K + k] = to_bf16_rne(x - bf16f(h));
+      const int64_t d = ws_index(panel, n, k, N, K);
+      hi[d] = h;
+      if (lo) lo[d] = to_bf16_rne(x - bf16f(h));
     }
   }
 }
@@ -60,7 +68,7 @@ typedef unsigned u32x4s __attribute__((ext_vector_type(4)));
 __device__ inline unsigned pack2(uint16_t a, uint16_t b) { return (unsigned)a | ((unsigned)b << 16); }
 
 __global__ void __launch_bounds__(256) k_split_rows8(const float *__restrict__ A, int64_t M, int64_t K, int64_t lda,
-                                                     uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+                                                     uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int panel) {
   const int64_t chunks = M * (K / 8);
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < chunks; c += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = 8 * c, i = e / K, k = e - i * K;
@@ -72,15 +80,16 @@ __global__ void __launch_bounds__(256) k_split_rows8(const float *__restrict__ A
       h[q] = to_bf16_rne(x[q]);
       l[q] = to_bf16_rne(x[q] - bf16f(h[q]));
     }
-    *(u32x4s *)(hi + e) = u32x4s{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
-    if (lo) *(u32x4s *)(lo + e) = u32x4s{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+    const int64_t d = ws_index(panel, i, k, M, K);  // 8 | k: the eight stay in one panel
+    *(u32x4s *)(hi + d) = u32x4s{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+    if (lo) *(u32x4s *)(lo + d) = u32x4s{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
   }
 }
 
 // B (K x N) -> N x K through a 64 (k) x 64 (n) LDS tile: rows of B are read
 // as float4, each output row n gets its 64 k as eight 16-byte stores.
 __global__ void __launch_bounds__(256) k_split_cols8(const float *__restrict__ B, int64_t K, int64_t N, int64_t ldb,
-                                                     uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+                                                     uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int panel) {
   __shared__ float t[64][65];
   const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
   for (int q = threadIdx.x; q < 64 * 16; q += 256) {  // 64 rows x 16 float4
@@ -111,8 +120,9 @@ __global__ void __launch_bounds__(256) k_split_cols8(const float *__restrict__ B
       h[j] = to_bf16_rne(x);
       l[j] = to_bf16_rne(x - bf16f(h[j]));
     }
-    *(u32x4s *)(hi + n * K + k) = u32x4s{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
-    if (lo) *(u32x4s *)(lo + n * K + k) = u32x4s{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+    const int64_t d = ws_index(panel, n, k, N, K);
+    *(u32x4s *)(hi + d) = u32x4s{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+    if (lo) *(u32x4s *)(lo + d) = u32x4s{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
   }
 }
 
@@ -128,20 +138,22 @@ hipError_t launch_bf16_split(const MatmulP &p, bool need_lo, hipStream_t st) {
       const int64_t chunks = p.M * (p.K / 8);
       const int g = (int)std::min<int64_t>((chunks + 255) / 256, 16384);
       hipLaunchKernelGGL(k_split_rows8, dim3(g), dim3(256), 0, st, p.A, p.M, p.K, p.lda, p.ah,
-                         need_lo ? p.al : nullptr);
+                         need_lo ? p.al : nullptr, p.panel);
     } else {
       const int64_t tot = p.M * p.K;
       const int g = (int)std::min<int64_t>((tot + 255) / 256, 8192);
       hipLaunchKernelGGL(k_split_rows, dim3(g), dim3(256), 0, st, p.A, p.M, p.K, p.lda, p.ah,
-                         need_lo ? p.al : nullptr);
+                         need_lo ? p.al : nullptr, p.panel);
     }
   }
   if (p.N > 0 && p.K > 0) {
     dim3 g((unsigned)((p.N + 63) / 64), (unsigned)((p.K + 63) / 64));
     if (vec_b)
-      hipLaunchKernelGGL(k_split_cols8, g, dim3(256), 0, st, p.B, p.K, p.N, p.ldb, p.bh, need_lo ? p.bl : nullptr);
+      hipLaunchKernelGGL(k_split_cols8, g, dim3(256), 0, st, p.B, p.K, p.N, p.ldb, p.bh, need_lo ? p.bl : nullptr,
+                         p.panel);
     else
-      hipLaunchKernelGGL(k_split_cols, g, dim3(256), 0, st, p.B, p.K, p.N, p.ldb, p.bh, need_lo ? p.bl : nullptr);
+      hipLaunchKernelGGL(k_split_cols, g, dim3(256), 0, st, p.B, p.K, p.N, p.ldb, p.bh, need_lo ? p.bl : nullptr,
+                         p.panel);
   }
   return hipGetLastError();
 }
@@ -183,6 +195,31 @@ __device__ inline void store_c(const MatmulP &p, int64_t row0, int64_t col0, con
       for (int r = 0; r < 16; ++r) {
         const int64_t row = row0 + wm * (BM / WM) + i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
         if (row < p.M && col < p.N) p.C[row * p.ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+// The same stores with the non-temporal hint (C is written once and not read
+// again here); the row and column tests are hoisted out of the element loop.
+// (A form through a buffer resource with __builtin_amdgcn_raw_buffer_store_b32
+// was compiled to stores that all took the same accumulator register.)
+template <int BM, int BN, int WM, int WN>
+__device__ inline void store_c_nt(const MatmulP &p, int64_t row0, int64_t col0, const f32x16 (&acc)[BM / WM / 32][BN / WN / 32]) {
+  constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t col = col0 + wn * (BN / WN) + j * 32 + (lane & 31);
+      const int64_t rb = row0 + wm * (BM / WM) + i * 32 + 4 * (lane >> 5);
+      float *cp = p.C + rb * p.ldc + col;
+      const bool cin = col < p.N;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int ro = 8 * (r / 4) + (r % 4);
+        if (cin && rb + ro < p.M) __builtin_nontemporal_store(acc[i][j][r], cp + ro * p.ldc);
       }
     }
 }
@@ -311,6 +348,158 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
   });
 }
 
+// 256 x 256 tiles on four waves (2 x 2), each wave 128 x 128 of C as 4 x 4
+// blocks of v_mfma_f32_32x32x16_bf16: twice the flops per fragment read from
+// LDS of the eight-wave tile above, whose fragment reads and staging writes
+// together kept the LDS close to saturation.
+//
+// Operands go from the workspace straight into LDS (buffer_load ... lds, no
+// staging registers; offsets past the operand read as zero, which also pads
+// the k tail) through a ring of five stages of BK = 32: the loads of the next
+// four steps are in flight while the matrix cores work on the current one.
+// The pre-pass writes the workspace in k-panels of 32 (ws_index layout 1),
+// so the 256 rows x 32 k one step needs are 16 KB of contiguous memory: with
+// rows of K, each row's 64 bytes were half of a cache line whose other half
+// the next step fetched again (measured on the load path alone: 48 us
+// against 78 us for 4096^3).
+//
+// LDS rows hold 32 k (64 bytes, four 16-byte chunks) of one row of A or B;
+// chunk c of row r is stored at chunk c ^ swz(r), swz(r) = r2 | (r1 ^ r3) << 1
+// over the bits of r: the sixteen consecutive rows a 16-lane phase of a
+// 16-byte read touches (4 rows per 256 bytes of banks) then fall on distinct
+// banks, and so do the eight rows of an 8-lane phase. Each step's sixteen
+// fragments are all read before its 32 matrix instructions are issued.
+//
+// Tiles are visited in groups of four tile rows, column by column inside a
+// group, so the 32 consecutive tiles one XCD runs at a time share four A
+// panels and eight B panels in that XCD's L2 (rather than two and sixteen).
+//
+// NSEG = 3 runs the split product as one bfloat16 GEMM over K' = 3K: the
+// k steps walk (A_lo, B_hi), then (A_hi, B_lo), then (A_hi, B_hi), so the
+// small terms are summed first, all in the float32 accumulators.
+constexpr int MMW_BK = 32, MMW_ROWB = 64, MMW_STAGES = 5, MMW_STAGE = 512 * MMW_ROWB;
+
+// s_waitcnt with only the vector-memory counter limited to n (other counters at their maximum)
+template <int N>
+__device__ inline void wait_vm() {
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+__device__ inline int mmw_swz(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1); }
+
+bool matmul_wide(const MatmulP &p, const SchedK &S) {
+  return p.kind != UPIR_BODY_MATMUL_F32 && S.tile[0] == 256 && S.tile[1] == 256 && S.U == 256;
+}
+
+template <int NSEG, bool ALIGNED>
+__global__ void __launch_bounds__(256) k_mm_bf16_wide(MatmulP p, SchedK S) {
+  constexpr int BM = 256, BN = 256, BK = MMW_BK, ROWB = MMW_ROWB, STAGE = MMW_STAGE, NST = MMW_STAGES;
+  constexpr int FM = 4, FN = 4;
+  constexpr int LOADS = 8;  // load instructions per wave per step (4 of A, 4 of B: 16 rows each)
+  static_assert(NST <= 5, "the waits below cover up to three later steps in flight");
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_w[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t K = p.K, KP = mm_kpad(K);
+  const int64_t seg_steps = (K + BK - 1) / BK, steps = NSEG * seg_steps;
+  const __amdgpu_buffer_rsrc_t rah = __builtin_amdgcn_make_buffer_rsrc((void *)p.ah, (short)0, (int)(p.M * KP * 2), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rbh = __builtin_amdgcn_make_buffer_rsrc((void *)p.bh, (short)0, (int)(p.N * KP * 2), 0x00020000);
+  const __amdgpu_buffer_rsrc_t ral = NSEG == 3 ? __builtin_amdgcn_make_buffer_rsrc((void *)p.al, (short)0, (int)(p.M * KP * 2), 0x00020000) : rah;
+  const __amdgpu_buffer_rsrc_t rbl = NSEG == 3 ? __builtin_amdgcn_make_buffer_rsrc((void *)p.bl, (short)0, (int)(p.N * KP * 2), 0x00020000) : rbh;
+  // this lane's place in every 16-row load group: row rr of the group,
+  // physical chunk lane % 4, which holds logical chunk lc
+  const int rr = lane >> 2, lc = (lane & 3) ^ mmw_swz(rr);
+  // fragment reads: row (lane mod 32) of a 32-row block, swizzle of that row
+  const int fr = lane & 31, fsw = mmw_swz(fr);
+
+  for_team_tiles(S, [&](int64_t m) {
+    // grouped tile order: groups of G tile rows, column-major inside a group
+    const int64_t nt0 = S.nt[0], nt1 = S.nt[1], G = 4;
+    const int64_t grp = m / (G * nt1), in = m - grp * G * nt1;
+    const int64_t gsz = std::min<int64_t>(G, nt0 - grp * G);
+    const int64_t trow = grp * G + in % gsz, tcol = in / gsz;
+    const int64_t row0 = (S.t0[0] + trow) * BM, col0 = (S.t0[1] + tcol) * BN;
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+    // this lane's byte offsets in k-panel 0 for its four row groups (32-bit:
+    // every operand is under 2 GiB); panel kt adds kt x rows x 64 bytes
+    uint32_t oa0[4], ob0[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int r = wave * 64 + g * 16 + rr;
+      oa0[g] = (uint32_t)(((row0 + r) * 32 + lc * 8) * 2);
+      ob0[g] = (uint32_t)(((col0 + r) * 32 + lc * 8) * 2);
+    }
+    const uint32_t pa = (uint32_t)(p.M * 64), pb = (uint32_t)(p.N * 64);  // bytes per k-panel
+    // issue the loads of step t into LDS stage buf (each wave: 64 rows of A, 64 of B)
+    auto load_step = [&](int64_t t, int buf) {
+      const int seg = NSEG == 3 ? (int)(t / seg_steps) : 0;
+      const uint32_t kt = (uint32_t)(t - (int64_t)seg * seg_steps);  // k-panel of the segment
+      const __amdgpu_buffer_rsrc_t ra = seg == 0 ? ral : rah, rb = seg == 1 ? rbl : rbh;
+      unsigned char *sA = lds_w + buf * STAGE, *sB = sA + BM * ROWB;
+      // ragged shapes: rows past M or N and k past K read as zero
+      const bool kin = ALIGNED || (int64_t)kt * BK + lc * 8 < K;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int r = wave * 64 + g * 16;  // first tile row of the group
+        uint32_t oa = oa0[g] + kt * pa, ob = ob0[g] + kt * pb;
+        if (!ALIGNED) {
+          if (!(row0 + r + rr < p.M && kin)) oa = 0x80000000u;
+          if (!(col0 + r + rr < p.N && kin)) ob = 0x80000000u;
+        }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (__attribute__((address_space(3))) void *)(sA + r * ROWB), 16, oa, 0, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (__attribute__((address_space(3))) void *)(sB + r * ROWB), 16, ob, 0, 0, 0);
+      }
+    };
+    __syncthreads();  // the previous tile's readers are done with LDS
+#pragma unroll
+    for (int q = 0; q < NST - 1; ++q)
+      if (q < steps) load_step(q, q);
+    for (int64_t t = 0; t < steps; ++t) {
+      // this thread's loads of step t have landed once at most the loads of
+      // the later steps already issued (up to NST - 2 of them) are pending
+      const int64_t later = std::min<int64_t>(steps - 1, t + NST - 2) - t;
+      if (later >= 3) wait_vm<3 * LOADS>();
+      else if (later == 2) wait_vm<2 * LOADS>();
+      else if (later == 1) wait_vm<LOADS>();
+      else wait_vm<0>();
+      // everyone's have, and step t - 1's fragment reads are done (each was
+      // waited for by the matrix instruction that used it). A bare barrier:
+      // __syncthreads() adds a workgroup release fence, which waits for every
+      // load in flight (the loads into LDS count as vector-memory operations)
+      // and would drain the ring at every step.
+      __asm__ volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      __asm__ volatile("" ::: "memory");
+      if (t + NST - 1 < steps) load_step(t + NST - 1, (int)((t + NST - 1) % NST));
+      const unsigned char *sA = lds_w + (int)(t % NST) * STAGE, *sB = sA + BM * ROWB;
+      bf16x8 a[BK / 16][FM], b[BK / 16][FN];
+#pragma unroll
+      for (int ks = 0; ks < BK / 16; ++ks) {
+        const int c = 2 * ks + (lane >> 5);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          a[ks][i] = *(const bf16x8 *)(sA + (wm * 128 + i * 32 + fr) * ROWB + ((c ^ fsw) << 4));
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          b[ks][j] = *(const bf16x8 *)(sB + (wn * 128 + j * 32 + fr) * ROWB + ((c ^ fsw) << 4));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ks = 0; ks < BK / 16; ++ks)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks][i], b[ks][j], acc[i][j], 0, 0, 0);
+    }
+    store_c_nt<BM, BN, 2, 2>(p, row0, col0, acc);
+  });
+}
+
 template <int BM, int BN, int WM, int WN, int BK>
 __global__ void __launch_bounds__(WM * WN * 64) k_mm_f32(MatmulP p, SchedK S) {
   constexpr int NTH = WM * WN * 64;
@@ -399,6 +588,7 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_f32(MatmulP p, SchedK S) {
 // Kernel configurations: (kind, tile) -> block size.
 struct MMConf { int kind, bm, bn, threads; };
 static const MMConf kMM[] = {
+    {UPIR_BODY_MATMUL_BF16, 256, 256, 256}, {UPIR_BODY_MATMUL_SPLIT3, 256, 256, 256},
     {UPIR_BODY_MATMUL_BF16, 256, 256, 512}, {UPIR_BODY_MATMUL_BF16, 128, 128, 256},
     {UPIR_BODY_MATMUL_SPLIT3, 256, 256, 512}, {UPIR_BODY_MATMUL_SPLIT3, 128, 128, 256},
     {UPIR_BODY_MATMUL_F32, 128, 128, 256}, {UPIR_BODY_MATMUL_F32, 256, 128, 512},
@@ -419,6 +609,9 @@ bool matmul_mfma_supports(const MatmulP &p, const LoopK &L, const SchedK &S) {
     if (p.K % 8) return false;
     if ((uintptr_t)p.ah % 16 || (uintptr_t)p.bh % 16) return false;
     if (p.kind == UPIR_BODY_MATMUL_SPLIT3 && ((uintptr_t)p.al % 16 || (uintptr_t)p.bl % 16)) return false;
+    // the wide tile addresses each operand with 32-bit buffer offsets
+    if (matmul_wide(p, S) && (p.M * mm_kpad(p.K) * 2 >= (1LL << 31) || p.N * mm_kpad(p.K) * 2 >= (1LL << 31)))
+      return false;
   }
   return true;
 }
@@ -438,12 +631,21 @@ static hipError_t go_mm(Kern k, const MatmulP &p, const SchedK &S, size_t lds, h
 hipError_t launch_matmul_mfma(const MatmulP &p, const LoopK &, const SchedK &S, hipStream_t st) {
   const int bm = S.tile[0], bn = S.tile[1];
   // LDS bytes = stages x (BM + BN) rows x pitch x 2 bytes (x 2 for the lo halves)
+  if (matmul_wide(p, S)) {
+    // whole tiles and whole k-panels: no bounds tests in the load loop
+    const bool al = p.M % 256 == 0 && p.N % 256 == 0 && p.K % MMW_BK == 0;
+    const size_t lds = MMW_STAGES * MMW_STAGE;
+    if (p.kind == UPIR_BODY_MATMUL_BF16)
+      return al ? go_mm(k_mm_bf16_wide<1, true>, p, S, lds, st) : go_mm(k_mm_bf16_wide<1, false>, p, S, lds, st);
+    return al ? go_mm(k_mm_bf16_wide<3, true>, p, S, lds, st) : go_mm(k_mm_bf16_wide<3, false>, p, S, lds, st);
+  }
   if (p.kind == UPIR_BODY_MATMUL_BF16) {
     if (bm == 256) return go_mm(k_mm_bf16<1, 256, 256, 2, 4, 64, 2>, p, S, 2 * (256 + 256) * 72 * 2, st);
     return go_mm(k_mm_bf16<1, 128, 128, 2, 2, 64, 2>, p, S, 2 * (128 + 128) * 72 * 2, st);
   }
   if (p.kind == UPIR_BODY_MATMUL_SPLIT3) {
-    if (bm == 256) return go_mm(k_mm_bf16<3, 256, 256, 2, 4, 32, 1>, p, S, 2 * (256 + 256) * 40 * 2, st);
+    // two stages of (A_hi, B_hi, A_lo, B_lo) x 256 rows x 80 bytes: all 160 KB of LDS
+    if (bm == 256) return go_mm(k_mm_bf16<3, 256, 256, 2, 4, 32, 2>, p, S, 2 * 2 * (256 + 256) * 40 * 2, st);
     return go_mm(k_mm_bf16<3, 128, 128, 2, 2, 32, 2>, p, S, 2 * 2 * (128 + 128) * 40 * 2, st);
   }
   if (bm == 256 && bn == 128) return go_mm(k_mm_f32<256, 128, 4, 2, 32>, p, S, (256 * 36 + 32 * 136) * 4, st);

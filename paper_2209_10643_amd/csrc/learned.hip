@@ -625,6 +625,7 @@ static std::vector<Cand> candidates(upir_ctx *c, const upir_loop_obj *lp) {
     case UPIR_BODY_MATMUL_BF16:
     case UPIR_BODY_MATMUL_SPLIT3:
       add(0, 256, UPIR_SCHED_STATIC, 0, 128, 128);
+      add(0, 256, UPIR_SCHED_STATIC, 0, 256, 256);
       add(0, 512, UPIR_SCHED_STATIC, 0, 256, 256);
       break;
     default:

@@ -339,8 +339,9 @@ static bool is_matmul(int32_t k) {
 
 extern "C" size_t upir_matmul_workspace_bytes(int32_t kind, int64_t M, int64_t N, int64_t K) {
   if (M < 0 || N < 0 || K < 0) return 0;
-  if (kind == UPIR_BODY_MATMUL_BF16) return (size_t)(M + N) * K * 2;
-  if (kind == UPIR_BODY_MATMUL_SPLIT3) return (size_t)(M + N) * K * 4;
+  // k is padded to the 32-wide panels one of the layouts uses
+  if (kind == UPIR_BODY_MATMUL_BF16) return (size_t)(M + N) * upir::mm_kpad(K) * 2;
+  if (kind == UPIR_BODY_MATMUL_SPLIT3) return (size_t)(M + N) * upir::mm_kpad(K) * 4;
   return 0;
 }
 
@@ -622,11 +623,12 @@ upir_status resolve_payload(upir_ctx *c, upir_loop_obj *lp, unsigned char *paylo
       p.kind = lp->kind;
       uint16_t *ws = (uint16_t *)(a.workspace ? a.workspace : lp->ws);
       if (lp->kind != UPIR_BODY_MATMUL_F32) {
+        const int64_t kp = mm_kpad(p.K);
         p.ah = ws;
-        p.bh = ws + p.M * p.K;
+        p.bh = ws + p.M * kp;
         if (lp->kind == UPIR_BODY_MATMUL_SPLIT3) {
-          p.al = p.bh + p.N * p.K;
-          p.bl = p.al + p.M * p.K;
+          p.al = p.bh + p.N * kp;
+          p.bl = p.al + p.M * kp;
         }
       }
       memcpy(payload, &p, sizeof p);
@@ -708,15 +710,17 @@ void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sc
     case UPIR_BODY_MATMUL_F32:
     case UPIR_BODY_MATMUL_BF16:
     case UPIR_BODY_MATMUL_SPLIT3: {
-      // MFMA tile configurations: float32 128 x 128 on 4 wavefronts,
-      // bfloat16 256 x 256 on 8 wavefronts (128 x 128 for small C)
+      // MFMA tile configurations: float32 128 x 128 on 4 wavefronts;
+      // bfloat16 256 x 256 on 4 wavefronts of 128 x 128 each; the split's
+      // three products 256 x 256 on 8 wavefronts (measured faster for it
+      // than the 4-wavefront tile over K' = 3K); 128 x 128 tiles for small C
       const bool f32 = lp->kind == UPIR_BODY_MATMUL_F32;
       const bool small = lp->cnt[0] * lp->cnt[1] < 2048LL * 2048;
       const int t = f32 || small ? 128 : 256;
       sc.policy = UPIR_SCHED_STATIC;
       sc.tile[0] = t;
       sc.tile[1] = t;
-      sp.num_units = t == 256 ? 512 : 256;
+      sp.num_units = (t == 256 && lp->kind == UPIR_BODY_MATMUL_SPLIT3) ? 512 : 256;
       sp.num_teams = 0;
       break;
     }
@@ -1003,7 +1007,8 @@ upir_status launch_plan(upir_ctx *c, upir_loop_obj *lp, const Plan &pl, bool for
     case V_FILTER7_TILE: e = launch_filter7_tile(*(const Filter7P *)pay, pl.L, S, R, c->stream); break;
     case V_MATVEC_WAVE: e = launch_matvec_wave(*(const MatvecP *)pay, pl.L, S, R, c->stream); break;
     case V_MATMUL_MFMA: {
-      const MatmulP &p = *(const MatmulP *)pay;
+      MatmulP p = *(const MatmulP *)pay;
+      p.panel = matmul_wide(p, S) ? 1 : 0;  // the pre-pass writes the layout the tile reads
       if (p.kind != UPIR_BODY_MATMUL_F32) e = launch_bf16_split(p, p.kind == UPIR_BODY_MATMUL_SPLIT3, c->stream);
       if (e == hipSuccess) e = launch_matmul_mfma(p, pl.L, S, c->stream);
       break;

@@ -26,7 +26,10 @@ struct MatmulP {
   const float *A, *B; float *C; int64_t M, N, K, lda, ldb, ldc;
   uint16_t *ah, *al, *bh, *bl;  // bfloat16 workspace (bh/bl stored transposed: N x K)
   int32_t kind;                 // 4 = f32, 5 = bf16, 6 = split3
+  int32_t panel;                // workspace layout: 0 rows of K; 1 k-panels of 32 (see kernels_matmul.hip)
 };
+// Workspace k extent: K rounded up to the 32-wide k-panels.
+__host__ __device__ inline int64_t mm_kpad(int64_t K) { return (K + 31) / 32 * 32; }
 struct MatvecP { const float *A; const float *x; float *y; int64_t cols, lda; };
 struct OwnerP { int32_t *out; };
 struct CoverP { int32_t *count; };
@@ -48,6 +51,8 @@ hipError_t launch_matmul_mfma(const MatmulP &p, const LoopK &L, const SchedK &S,
 bool matmul_mfma_supports(const MatmulP &p, const LoopK &L, const SchedK &S);
 // BF16 pre-pass: A (M x K) -> ah, al; B (K x N) -> bh, bl transposed (N x K).
 hipError_t launch_bf16_split(const MatmulP &p, bool need_lo, hipStream_t st);
+// The 256 x 256 four-wavefront bfloat16 tile (it reads the k-panel workspace layout).
+bool matmul_wide(const MatmulP &p, const SchedK &S);
 
 // Jacobi tiled kernel constraints.
 bool jacobi_tile_supports(const JacobiP &p, const LoopK &L, const SchedK &S);
