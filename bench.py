@@ -69,13 +69,13 @@ class Timer:
 # ------------------------------------------------------------------ Jacobi
 # HBM traffic per 4096^2 sweep of k_jacobi_tile, keyed by (tile rows, units):
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a 1 GiB copy), bytes,
-# from profiles/jacobi5_4096_hbm_traffic.md. Valid for the kernel as profiled.
+# from profiles/jacobi5_4096_hbm_traffic.md (re-taken whenever the kernel changes).
 JACOBI_4096_TRAFFIC = {
-    (8, 64): 142904433, (8, 128): 135163693, (8, 256): 135231792, (8, 512): 135703210,
-    (16, 64): 143522926, (16, 128): 142072313, (16, 256): 135023410, (16, 512): 135219782,
-    (32, 64): 139220740, (32, 128): 143329295, (32, 256): 142956880, (32, 512): 135002904,
-    (64, 64): 136930246, (64, 128): 139340149, (64, 256): 143342950, (64, 512): 140122076,
-    (128, 64): 136003482, (128, 128): 136952144, (128, 256): 139171625, (128, 512): 143239116,
+    (8, 64): 143890192, (8, 128): 135156624, (8, 256): 135218826, (8, 512): 135693600,
+    (16, 64): 143543925, (16, 128): 141761173, (16, 256): 135000416, (16, 512): 135172896,
+    (32, 64): 139317050, (32, 128): 143373477, (32, 256): 142459741, (32, 512): 134985744,
+    (64, 64): 136936149, (64, 128): 139121904, (64, 256): 143289009, (64, 512): 140515427,
+    (128, 64): 135991989, (128, 128): 136956768, (128, 256): 139148192, (128, 512): 143243109,
 }
 
 
