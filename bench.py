@@ -248,6 +248,23 @@ def bench_axpy(torch, ctx, timer, reps=1000):
     out = {"n": n, "us_per_loop": round(per * 1e3, 3), "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
            "variant": U.VARIANTS[v], "teams": sp.num_teams, "units": sp.num_units,
            "note": "12 MiB working set: cache resident (L2 / MALL), 1000 back-to-back loops in one graph"}
+    # the same loop with the split (async) reduction: each kernel leaves one
+    # partial per wavefront and the cross-workgroup fold rides on the next
+    # loop's kernel, so no kernel waits for the others' partials
+    ra = torch.zeros(1, dtype=torch.float64, device="cuda")
+    la = ctx.loop(U.UPIR_BODY_AXPY, args, [(0, n, 1)], None, H.make_red(U.UPIR_RED_SUM, ra.data_ptr(), async_=True))
+    ctx.launch(la)
+    ctx.sync()
+    ctx.graph_begin()
+    for _ in range(reps):
+        ctx.launch(la)
+    ga = ctx.graph_end()
+    ctx.graph_launch(ga)
+    per_a = timer.time(lambda: ctx.graph_launch(ga), 3) / reps
+    ctx.graph_destroy(ga)
+    ctx.free(la)
+    gba = 12 * n / (per_a * 1e-3) / 1e9
+    out["async_fold"] = {"us_per_loop": round(per_a * 1e3, 3), "GBps": round(gba, 1), "frac": round(gba / HBM_PEAK_GBS, 4)}
     # one loop from the initial y against the oracle: y' bit for bit, the fused sum
     from oracle import bodies
     y.copy_(y0)
