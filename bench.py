@@ -644,13 +644,13 @@ def batched_vs_oracle(tasks, outs, seed=12345, every=16):
 
 def training_graph_spec(seed, b):
     """Task graph b of the cost model's training set (never the benchmark's
-    graph): task count in {256, 512, 1024, 2048}, lengths floor(2^u) with u
-    uniform in [8, lmax], lmax in {16, 18, 20, 22}, kinds drawn with random
+    graph): task count in {512, 1024, 2048, 2048}, lengths floor(2^u) with u
+    uniform in [8, lmax], lmax in {18, 20, 22, 22}, kinds drawn with random
     weights over AXPY / SUM / MATVEC, edges i < j with probability
     d / (n - 1), d in {0, 1, 2, 4, 6}."""
     r = synth.uniform01_f64(seed, 3000 + b, 8)
-    n = (256, 512, 1024, 2048)[int(r[0] * 4) % 4]
-    lmax = (16, 18, 20, 22)[int(r[1] * 4) % 4]
+    n = (512, 1024, 2048, 2048)[int(r[0] * 4) % 4]
+    lmax = (18, 20, 22, 22)[int(r[1] * 4) % 4]
     d = (0, 1, 2, 4, 6)[int(r[2] * 5) % 5]
     w = np.array([0.2 + r[3], 0.2 + r[4], 0.2 + r[5]])
     cum = np.cumsum(w / w.sum())
@@ -666,7 +666,7 @@ def training_graph_spec(seed, b):
     return kinds, lens, preds
 
 
-def tune_training_graphs(torch, ctx, n_graphs=24, seed=777, reps=3):
+def tune_training_graphs(torch, ctx, n_graphs=40, seed=777, reps=3):
     """Rows of the timing table for task graphs: every engine-schedule
     candidate of each training graph timed by the batch tuner. Returns
     (graph keys, time of the default, of the tuner's best) per graph."""

@@ -385,7 +385,8 @@ upir_status upir_engine_sched_resolve(upir_ctx *ctx, upir_engine_sched *out, int
 upir_status upir_engine_candidate(upir_ctx *ctx, int32_t idx, upir_engine_sched *out, float *feat32);
 /* Exhaustive batch tuner: run the pending task graph with the batched
  * executor once per candidate and then `reps` times between HIP events,
- * record one timing-table row per candidate (median time), and remember the
+ * record one timing-table row per candidate (log2 of its median time over
+ * the default candidate's: graph rows hold relative costs) and remember the
  * fastest for graphs of this shape. The tasks stay pending. The runs execute
  * the tasks: a task that updates its data in place (AXPY) is applied
  * (reps + 1) x 27 times, so callers restore such data before the taskwait

@@ -793,7 +793,17 @@ uint64_t batch_key(const upir_ctx *c) {
 }
 
 // 32 features of (pending task graph, engine candidate). Slot 30 marks a
-// graph row (loop rows leave it 0).
+// graph row (loop rows leave it 0). The candidate enters as one one-hot per
+// body over that body's three tile choices, weighted by the body's share of
+// the graph's bytes, so that a choice's effect on the graph's relative cost
+// is close to additive in the features; then the work items each body makes.
+static int choice_index(int k, int64_t tile) {
+  static const int64_t opts[3][3] = {{8192, 16384, 32768}, {16384, 32768, 65536}, {32, 64, 128}};
+  for (int q = 0; q < 3; ++q)
+    if (opts[k][q] == tile) return q;
+  return -1;
+}
+
 void batch_features(const upir_ctx *c, const upir_engine_sched &es, float f[32]) {
   for (int i = 0; i < 32; ++i) f[i] = 0.0f;
   const size_t n = c->tasks.size();
@@ -822,9 +832,9 @@ void batch_features(const upir_ctx *c, const upir_engine_sched &es, float f[32])
   for (int k = 0; k < 3; ++k) {
     f[k] = (float)(cnt[k] / N);
     f[3 + k] = (float)(bytes[k] / B);
-    f[12 + k] = (float)(lg((double)class_tile(es, k)) / 24);
-    f[15 + k] = (float)(lg(items[k] + 1) / 24);
-    f[20 + k] = (float)(lg(items[k] > 0 ? bytes[k] / items[k] : 1.0) / 32);
+    const int q = choice_index(k, class_tile(es, k));
+    if (q >= 0) f[12 + 3 * k + q] = (float)(bytes[k] / B);
+    f[21 + k] = (float)(lg(items[k] + 1) / 24);
   }
   f[6] = (float)(lg(N) / 16);
   f[7] = (float)(lg(B) / 40);
@@ -832,9 +842,7 @@ void batch_features(const upir_ctx *c, const upir_engine_sched &es, float f[32])
   f[9] = (float)(lgmax / 32);
   f[10] = (float)(edges / N / 8);
   f[11] = (float)(dmax / 64.0);
-  f[18] = (float)(lg(I) / 24);
-  f[19] = (float)(lg(I / grid) / 16);
-  f[23] = (float)(lg(grid) / 16);
+  f[24] = (float)(lg(I / grid) / 16);
   f[30] = 1.0f;
 }
 

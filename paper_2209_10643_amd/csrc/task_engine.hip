@@ -759,6 +759,12 @@ extern "C" upir_status upir_tune_batched(upir_ctx *c, int32_t reps, upir_engine_
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (st) return st;
+  // A graph row records its time relative to the default schedule (candidate
+  // 0): the candidates of one graph differ by a few percent while whole
+  // graphs differ by orders of magnitude, so relative costs are what the
+  // model can learn to rank (and ranking is all the choice needs).
+  const float base = rows[0].log2_us;
+  for (TuneRow &r : rows) r.log2_us -= base;
   c->db.insert(c->db.end(), rows.begin(), rows.end());
   c->tuned_engine[key] = std::make_pair(cs[bi], bus);
   if (best) *best = cs[bi];
