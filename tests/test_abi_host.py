@@ -321,6 +321,9 @@ def test_status_strings():
     for s in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert U.lib().upir_strerror(s)
     assert U.upir_matmul_workspace_bytes(U.UPIR_BODY_MATMUL_SPLIT3, 4096, 4096, 4096) == 2 * 4096 * 4096 * 4
+    # k is padded to the 32-wide panels of the four-wavefront tile's layout
+    assert U.upir_matmul_workspace_bytes(U.UPIR_BODY_MATMUL_BF16, 17, 33, 65) == (17 + 33) * 96 * 2
+    assert U.upir_matmul_workspace_bytes(U.UPIR_BODY_MATMUL_SPLIT3, 17, 33, 64) == (17 + 33) * 64 * 4
 
 
 def test_update_task_graph_and_validation(hctx):

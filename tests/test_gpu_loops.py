@@ -618,16 +618,19 @@ def test_matmul_generic_parity(ctx, kind, tol, M, N, K):
     C_ = tC.cpu().numpy()
     assert bodies.frob_rel(C_, bodies.matmul(A, B)) <= tol
     if kind != U.UPIR_BODY_MATMUL_F32:
+        # workspace regions of M x K' (A) and N x K' (B) elements, K' = K
+        # rounded up to 32; the generic kernel's layout is rows of K in each
         w = ws.cpu().numpy().view(np.uint16)
+        Kp = (K + 31) // 32 * 32
         ah = w[:M * K].reshape(M, K)
-        bh = w[M * K:M * K + N * K].reshape(N, K)
+        bh = w[M * Kp:M * Kp + N * K].reshape(N, K)
         hiA, loA = bodies.split_bf16(A)
         hiB, loB = bodies.split_bf16(B)
         assert np.array_equal(ah, (hiA.view(np.uint32) >> 16).astype(np.uint16))
         assert np.array_equal(bh, (hiB.T.view(np.uint32) >> 16).astype(np.uint16))
         if kind == U.UPIR_BODY_MATMUL_SPLIT3:
-            al = w[(M + N) * K:(2 * M + N) * K].reshape(M, K)
-            bl = w[(2 * M + N) * K:2 * (M + N) * K].reshape(N, K)
+            al = w[(M + N) * Kp:(M + N) * Kp + M * K].reshape(M, K)
+            bl = w[(2 * M + N) * Kp:(2 * M + N) * Kp + N * K].reshape(N, K)
             assert np.array_equal(al, (loA.view(np.uint32) >> 16).astype(np.uint16))
             assert np.array_equal(bl, (np.ascontiguousarray(loB.T).view(np.uint32) >> 16).astype(np.uint16))
         emul = bodies.matmul_bf16(A, B) if kind == U.UPIR_BODY_MATMUL_BF16 else bodies.matmul_split3(A, B)
