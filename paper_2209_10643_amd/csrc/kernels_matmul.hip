@@ -224,6 +224,14 @@ __device__ inline void store_c_nt(const MatmulP &p, int64_t row0, int64_t col0, 
     }
 }
 
+// Chunk swizzle of LDS rows of 64 bytes (four 16-byte chunks): chunk c of
+// row r is stored at chunk c ^ swz(r), swz(r) = r2 | (r1 ^ r3) << 1 over the
+// bits of r. The sixteen consecutive rows a 16-lane phase of a 16-byte read
+// touches (4 rows per 256 bytes of banks) then fall on distinct banks, and so
+// do the eight rows of an 8-lane phase (2 rows per 128 bytes); a phase that
+// writes four whole rows covers the banks once whatever the swizzle.
+__device__ inline int mmw_swz(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1); }
+
 // Tiles owned by this team under the tiled schedule.
 template <class F>
 __device__ inline void for_team_tiles(const SchedK &S, F &&f) {
@@ -242,7 +250,10 @@ __device__ inline void for_team_tiles(const SchedK &S, F &&f) {
 template <int NPROD, int BM, int BN, int WM, int WN, int BK, int STAGES>
 __global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
   constexpr int NTH = WM * WN * 64;
-  constexpr int PITCH = BK + 8;  // halfwords per LDS row (16-byte multiple)
+  // LDS rows: 64 k with 8 halfwords of padding (no conflicts), or 32 k with
+  // the chunk swizzle (padded 80-byte rows had conflicting staging writes)
+  constexpr bool SWZ = BK == 32;
+  constexpr int PITCH = SWZ ? BK : BK + 8;  // halfwords per LDS row (16-byte multiple)
   constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
   constexpr int CPR = BK / 8;                    // 16-byte chunks per row
   constexpr int CA = BM * CPR / NTH, CB = BN * CPR / NTH;
@@ -285,13 +296,13 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
       uint16_t *sAl = sBh + BN * PITCH, *sBl = sAl + BM * PITCH;
 #pragma unroll
       for (int q = 0; q < CA; ++q) {
-        const int c = tid + q * NTH, r = c / CPR, kc = c % CPR;
+        const int c = tid + q * NTH, r = c / CPR, kc = SWZ ? (c % CPR) ^ mmw_swz(c / CPR) : c % CPR;
         *(u32x4 *)(sAh + r * PITCH + kc * 8) = ra[q];
         if (NPROD == 3) *(u32x4 *)(sAl + r * PITCH + kc * 8) = ral[q];
       }
 #pragma unroll
       for (int q = 0; q < CB; ++q) {
-        const int c = tid + q * NTH, r = c / CPR, kc = c % CPR;
+        const int c = tid + q * NTH, r = c / CPR, kc = SWZ ? (c % CPR) ^ mmw_swz(c / CPR) : c % CPR;
         *(u32x4 *)(sBh + r * PITCH + kc * 8) = rb[q];
         if (NPROD == 3) *(u32x4 *)(sBl + r * PITCH + kc * 8) = rbl[q];
       }
@@ -308,7 +319,8 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
       const uint16_t *sAl = sBh + BN * PITCH, *sBl = sAl + BM * PITCH;
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 16) {
-        const int koff = ks + 8 * (lane >> 5);
+        // rows read here are = lane mod 32 (mod 32): the swizzle of the row is that of lane mod 32
+        const int koff = SWZ ? (((ks >> 3) + (lane >> 5)) ^ mmw_swz(lane & 31)) * 8 : ks + 8 * (lane >> 5);
         bf16x8 a[FM], b[FN], al[NPROD == 3 ? FM : 1], bl[NPROD == 3 ? FN : 1];
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
@@ -384,8 +396,6 @@ template <int N>
 __device__ inline void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
-
-__device__ inline int mmw_swz(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1); }
 
 bool matmul_wide(const MatmulP &p, const SchedK &S) {
   return p.kind != UPIR_BODY_MATMUL_F32 && S.tile[0] == 256 && S.tile[1] == 256 && S.U == 256;
@@ -644,9 +654,9 @@ hipError_t launch_matmul_mfma(const MatmulP &p, const LoopK &, const SchedK &S, 
     return go_mm(k_mm_bf16<1, 128, 128, 2, 2, 64, 2>, p, S, 2 * (128 + 128) * 72 * 2, st);
   }
   if (p.kind == UPIR_BODY_MATMUL_SPLIT3) {
-    // two stages of (A_hi, B_hi, A_lo, B_lo) x 256 rows x 80 bytes: all 160 KB of LDS
-    if (bm == 256) return go_mm(k_mm_bf16<3, 256, 256, 2, 4, 32, 2>, p, S, 2 * 2 * (256 + 256) * 40 * 2, st);
-    return go_mm(k_mm_bf16<3, 128, 128, 2, 2, 32, 2>, p, S, 2 * 2 * (128 + 128) * 40 * 2, st);
+    // two stages of (A_hi, B_hi, A_lo, B_lo) x rows x 64 bytes (swizzled, unpadded)
+    if (bm == 256) return go_mm(k_mm_bf16<3, 256, 256, 2, 4, 32, 2>, p, S, 2 * 2 * (256 + 256) * 32 * 2, st);
+    return go_mm(k_mm_bf16<3, 128, 128, 2, 2, 32, 2>, p, S, 2 * 2 * (128 + 128) * 32 * 2, st);
   }
   if (bm == 256 && bn == 128) return go_mm(k_mm_f32<256, 128, 4, 2, 32>, p, S, (256 * 36 + 32 * 136) * 4, st);
   return go_mm(k_mm_f32<128, 128, 2, 2, 32>, p, S, (128 * 36 + 32 * 136) * 4, st);
