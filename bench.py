@@ -559,6 +559,14 @@ def bench_matmul(torch, ctx, timer, reps=5):
                      "variant": U.VARIANTS[v],
                      "tile": [sc.tile[0], sc.tile[1]], "includes_bf16_prepass": name != "f32"}
         ctx.free(lp)
+    # context, not the product path: the vendor BF16 GEMM (torch.matmul, which
+    # calls hipBLASLt) on the same operands rounded to bfloat16, bfloat16 out
+    a16, b16 = tA.to(torch.bfloat16).contiguous(), tB.to(torch.bfloat16).contiguous()
+    torch.matmul(a16, b16)
+    ms = timer.time(lambda: torch.matmul(a16, b16), reps)
+    out["reference_torch_matmul_bf16"] = {"ms": round(ms, 4), "TFLOPs": round(2 * n ** 3 / (ms * 1e-3) / 1e12, 1),
+                                          "note": "torch.matmul (hipBLASLt) on bfloat16 copies, bfloat16 C "
+                                                  "(half the bytes of C stored); no pre-pass; context only"}
     return out
 
 

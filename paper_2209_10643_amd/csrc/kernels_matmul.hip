@@ -200,10 +200,12 @@ __device__ inline void store_c(const MatmulP &p, int64_t row0, int64_t col0, con
 }
 
 // The same stores with the non-temporal hint (C is written once and not read
-// again here); the row and column tests are hoisted out of the element loop.
+// again here); the row and column tests are hoisted out of the element loop,
+// and left out for tiles known to be whole (CHECK false: each test became a
+// branch around its store).
 // (A form through a buffer resource with __builtin_amdgcn_raw_buffer_store_b32
 // was compiled to stores that all took the same accumulator register.)
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool CHECK = true>
 __device__ inline void store_c_nt(const MatmulP &p, int64_t row0, int64_t col0, const f32x16 (&acc)[BM / WM / 32][BN / WN / 32]) {
   constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -219,7 +221,7 @@ __device__ inline void store_c_nt(const MatmulP &p, int64_t row0, int64_t col0, 
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int ro = 8 * (r / 4) + (r % 4);
-        if (cin && rb + ro < p.M) __builtin_nontemporal_store(acc[i][j][r], cp + ro * p.ldc);
+        if (!CHECK || (cin && rb + ro < p.M)) __builtin_nontemporal_store(acc[i][j][r], cp + ro * p.ldc);
       }
     }
 }
@@ -367,20 +369,32 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
 //
 // Operands go from the workspace straight into LDS (buffer_load ... lds, no
 // staging registers; offsets past the operand read as zero, which also pads
-// the k tail) through a ring of five stages of BK = 32: the loads of the next
-// four steps are in flight while the matrix cores work on the current one.
-// The pre-pass writes the workspace in k-panels of 32 (ws_index layout 1),
-// so the 256 rows x 32 k one step needs are 16 KB of contiguous memory: with
-// rows of K, each row's 64 bytes were half of a cache line whose other half
-// the next step fetched again (measured on the load path alone: 48 us
-// against 78 us for 4096^3).
+// the k tail) through a ring of five stages of BK = 32. The pre-pass writes
+// the workspace in k-panels of 32 (ws_index layout 1), so the 256 rows x 32 k
+// one step needs are 16 KB of contiguous memory: with rows of K, each row's
+// 64 bytes were half of a cache line whose other half the next step fetched
+// again (measured on the load path alone: 48 us against 78 us for 4096^3).
+// A lane's offset inside a panel is fixed; the panel's offset is the scalar
+// offset of the load.
 //
 // LDS rows hold 32 k (64 bytes, four 16-byte chunks) of one row of A or B;
 // chunk c of row r is stored at chunk c ^ swz(r), swz(r) = r2 | (r1 ^ r3) << 1
 // over the bits of r: the sixteen consecutive rows a 16-lane phase of a
 // 16-byte read touches (4 rows per 256 bytes of banks) then fall on distinct
-// banks, and so do the eight rows of an 8-lane phase. Each step's sixteen
-// fragments are all read before its 32 matrix instructions are issued.
+// banks, and so do the eight rows of an 8-lane phase.
+//
+// Software pipeline over k steps, one phase per step u: wait until step u's
+// loads have landed (each wave's own count, then a barrier for everyone's),
+// issue four matrix instructions of step u - 1, issue the loads of step
+// u + 4 into the slot step u - 1 used, then read step u's sixteen fragments
+// into the second register set spread over the next sixteen matrix
+// instructions, and finish step u - 1's 32. The matrix cores are thus never
+// left waiting on LDS reads (reading all fragments before the MFMAs left them
+// idle a third of the time), and the loads run four steps ahead. Each wave's
+// reads of step u - 1 are complete before the barrier of phase u, so that
+// slot is free for reuse by then. Steps past the last one load panel 0 again
+// into a slot nobody reads, which keeps the wait counts the same in every
+// phase; the last wait of a tile drains them before LDS is reused.
 //
 // Tiles are visited in groups of four tile rows, column by column inside a
 // group, so the 32 consecutive tiles one XCD runs at a time share four A
@@ -389,6 +403,8 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_bf16(MatmulP p, SchedK S) {
 // NSEG = 3 runs the split product as one bfloat16 GEMM over K' = 3K: the
 // k steps walk (A_lo, B_hi), then (A_hi, B_lo), then (A_hi, B_hi), so the
 // small terms are summed first, all in the float32 accumulators.
+// EVEN: the step count (NSEG x ceil(K / 32)) is even, which fixes which of
+// the two fragment register sets holds the last step.
 constexpr int MMW_BK = 32, MMW_ROWB = 64, MMW_STAGES = 5, MMW_STAGE = 512 * MMW_ROWB;
 
 // s_waitcnt with only the vector-memory counter limited to n (other counters at their maximum)
@@ -396,22 +412,26 @@ template <int N>
 __device__ inline void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
+// s_waitcnt lgkmcnt(0) (LDS reads of this wave complete), other counters at their maximum
+__device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4)); }
 
 bool matmul_wide(const MatmulP &p, const SchedK &S) {
   return p.kind != UPIR_BODY_MATMUL_F32 && S.tile[0] == 256 && S.tile[1] == 256 && S.U == 256;
 }
 
-template <int NSEG, bool ALIGNED>
+template <int NSEG, bool ALIGNED, bool EVEN>
 __global__ void __launch_bounds__(256) k_mm_bf16_wide(MatmulP p, SchedK S) {
-  constexpr int BM = 256, BN = 256, BK = MMW_BK, ROWB = MMW_ROWB, STAGE = MMW_STAGE, NST = MMW_STAGES;
-  constexpr int FM = 4, FN = 4;
-  constexpr int LOADS = 8;  // load instructions per wave per step (4 of A, 4 of B: 16 rows each)
-  static_assert(NST <= 5, "the waits below cover up to three later steps in flight");
+  constexpr int BM = 256, ROWB = MMW_ROWB, STAGE = MMW_STAGE, NST = MMW_STAGES;
+  constexpr int AHEAD = NST - 1;   // phase u issues the loads of step u + AHEAD
+  constexpr int LOADS = 8;         // load instructions per wave per step (4 of A, 4 of B: 16 rows each)
+  constexpr int PRE = 4, SPAN = 16;  // MFMAs before the first fragment read; MFMAs the reads spread over
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_w[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
   const int64_t K = p.K, KP = mm_kpad(K);
-  const int64_t seg_steps = (K + BK - 1) / BK, steps = NSEG * seg_steps;
+  // the host admits this kernel only with every operand under 2 GiB, so steps fit in int
+  const int seg_steps = (int)((K + MMW_BK - 1) / MMW_BK), steps = NSEG * seg_steps;
   const __amdgpu_buffer_rsrc_t rah = __builtin_amdgcn_make_buffer_rsrc((void *)p.ah, (short)0, (int)(p.M * KP * 2), 0x00020000);
   const __amdgpu_buffer_rsrc_t rbh = __builtin_amdgcn_make_buffer_rsrc((void *)p.bh, (short)0, (int)(p.N * KP * 2), 0x00020000);
   const __amdgpu_buffer_rsrc_t ral = NSEG == 3 ? __builtin_amdgcn_make_buffer_rsrc((void *)p.al, (short)0, (int)(p.M * KP * 2), 0x00020000) : rah;
@@ -419,8 +439,13 @@ __global__ void __launch_bounds__(256) k_mm_bf16_wide(MatmulP p, SchedK S) {
   // this lane's place in every 16-row load group: row rr of the group,
   // physical chunk lane % 4, which holds logical chunk lc
   const int rr = lane >> 2, lc = (lane & 3) ^ mmw_swz(rr);
-  // fragment reads: row (lane mod 32) of a 32-row block, swizzle of that row
-  const int fr = lane & 31, fsw = mmw_swz(fr);
+  // fragment reads: row (lane mod 32) of a 32-row block, k group lane / 32;
+  // byte offsets inside a stage for k half 0 / 1 of A and of B
+  const int fr = lane & 31, fsw = mmw_swz(fr), hg = lane >> 5;
+  const int fa0 = (wm * 128 + fr) * ROWB + ((hg ^ fsw) << 4), fa1 = (wm * 128 + fr) * ROWB + (((2 + hg) ^ fsw) << 4);
+  const int fb0 = BM * ROWB + (wn * 128 + fr) * ROWB + ((hg ^ fsw) << 4);
+  const int fb1 = BM * ROWB + (wn * 128 + fr) * ROWB + (((2 + hg) ^ fsw) << 4);
+  const uint32_t pa = (uint32_t)(p.M * 64), pb = (uint32_t)(p.N * 64);  // bytes per k-panel
 
   for_team_tiles(S, [&](int64_t m) {
     // grouped tile order: groups of G tile rows, column-major inside a group
@@ -428,85 +453,117 @@ __global__ void __launch_bounds__(256) k_mm_bf16_wide(MatmulP p, SchedK S) {
     const int64_t grp = m / (G * nt1), in = m - grp * G * nt1;
     const int64_t gsz = std::min<int64_t>(G, nt0 - grp * G);
     const int64_t trow = grp * G + in % gsz, tcol = in / gsz;
-    const int64_t row0 = (S.t0[0] + trow) * BM, col0 = (S.t0[1] + tcol) * BN;
-    f32x16 acc[FM][FN];
+    const int64_t row0 = (S.t0[0] + trow) * BM, col0 = (S.t0[1] + tcol) * BM;
+    f32x16 acc[4][4];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j) acc[i][j] = f32x16{};
+      for (int j = 0; j < 4; ++j) acc[i][j] = f32x16{};
     // this lane's byte offsets in k-panel 0 for its four row groups (32-bit:
-    // every operand is under 2 GiB); panel kt adds kt x rows x 64 bytes
+    // every operand is under 2 GiB), and whether its rows exist
     uint32_t oa0[4], ob0[4];
+    bool va[4], vb[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int r = wave * 64 + g * 16 + rr;
       oa0[g] = (uint32_t)(((row0 + r) * 32 + lc * 8) * 2);
       ob0[g] = (uint32_t)(((col0 + r) * 32 + lc * 8) * 2);
+      va[g] = ALIGNED || row0 + r < p.M;
+      vb[g] = ALIGNED || col0 + r < p.N;
     }
-    const uint32_t pa = (uint32_t)(p.M * 64), pb = (uint32_t)(p.N * 64);  // bytes per k-panel
-    // issue the loads of step t into LDS stage buf (each wave: 64 rows of A, 64 of B)
-    auto load_step = [&](int64_t t, int buf) {
-      const int seg = NSEG == 3 ? (int)(t / seg_steps) : 0;
-      const uint32_t kt = (uint32_t)(t - (int64_t)seg * seg_steps);  // k-panel of the segment
+    // the next step to load: its index, segment and k-panel (scalars)
+    int lt = 0, lseg = 0, lkt = 0;
+    auto load_next = [&](int slot) {
+      const bool live = lt < steps;
+      const int kt = live ? lkt : 0, seg = NSEG == 3 && live ? lseg : 0;
       const __amdgpu_buffer_rsrc_t ra = seg == 0 ? ral : rah, rb = seg == 1 ? rbl : rbh;
-      unsigned char *sA = lds_w + buf * STAGE, *sB = sA + BM * ROWB;
+      const uint32_t sa = (uint32_t)kt * pa, sb = (uint32_t)kt * pb;
       // ragged shapes: rows past M or N and k past K read as zero
-      const bool kin = ALIGNED || (int64_t)kt * BK + lc * 8 < K;
+      const bool kin = ALIGNED || (int64_t)kt * MMW_BK + lc * 8 < K;
+      unsigned char *sA = lds_w + slot * STAGE + wv * 64 * ROWB, *sB = sA + BM * ROWB;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int r = wave * 64 + g * 16;  // first tile row of the group
-        uint32_t oa = oa0[g] + kt * pa, ob = ob0[g] + kt * pb;
-        if (!ALIGNED) {
-          if (!(row0 + r + rr < p.M && kin)) oa = 0x80000000u;
-          if (!(col0 + r + rr < p.N && kin)) ob = 0x80000000u;
-        }
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (__attribute__((address_space(3))) void *)(sA + r * ROWB), 16, oa, 0, 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (__attribute__((address_space(3))) void *)(sB + r * ROWB), 16, ob, 0, 0, 0);
+        const uint32_t oa = ALIGNED || (va[g] && kin) ? oa0[g] : 0x80000000u;
+        const uint32_t ob = ALIGNED || (vb[g] && kin) ? ob0[g] : 0x80000000u;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (__attribute__((address_space(3))) void *)(sA + g * 16 * ROWB), 16, oa, sa, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (__attribute__((address_space(3))) void *)(sB + g * 16 * ROWB), 16, ob, sb, 0, 0);
+      }
+      ++lt;
+      if (++lkt == seg_steps) {
+        lkt = 0;
+        ++lseg;
       }
     };
-    __syncthreads();  // the previous tile's readers are done with LDS
+    // fragment q of a step (k half q / 8; 0-3: A blocks, 4-7: B blocks) from the stage at byte sbase
+    auto read_one = [&](int sbase, bf16x8 (&Y)[2][8], int q) {
+      const int ks = q >> 3, x = q & 7;
+      const int off = x < 4 ? (ks ? fa1 : fa0) + x * 32 * ROWB : (ks ? fb1 : fb0) + (x - 4) * 32 * ROWB;
+      Y[ks][x] = *(const bf16x8 *)(lds_w + sbase + off);
+    };
+    // matrix instructions lo..hi-1 of a step: k half q / 16, block (q / 4 mod 4, q mod 4)
+    auto mfmas = [&](bf16x8 (&X)[2][8], int lo, int hi) {
 #pragma unroll
-    for (int q = 0; q < NST - 1; ++q)
-      if (q < steps) load_step(q, q);
-    for (int64_t t = 0; t < steps; ++t) {
-      // this thread's loads of step t have landed once at most the loads of
-      // the later steps already issued (up to NST - 2 of them) are pending
-      const int64_t later = std::min<int64_t>(steps - 1, t + NST - 2) - t;
-      if (later >= 3) wait_vm<3 * LOADS>();
-      else if (later == 2) wait_vm<2 * LOADS>();
-      else if (later == 1) wait_vm<LOADS>();
-      else wait_vm<0>();
-      // everyone's have, and step t - 1's fragment reads are done (each was
-      // waited for by the matrix instruction that used it). A bare barrier:
-      // __syncthreads() adds a workgroup release fence, which waits for every
-      // load in flight (the loads into LDS count as vector-memory operations)
-      // and would drain the ring at every step.
+      for (int q = lo; q < hi; ++q) {
+        const int ks = q >> 4, i = (q >> 2) & 3, j = q & 3;
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X[ks][i], X[ks][4 + j], acc[i][j], 0, 0, 0);
+      }
+    };
+    auto bar = [] {
+      // a bare barrier: __syncthreads() adds a workgroup release fence, which
+      // waits for every load in flight (the loads into LDS count as
+      // vector-memory operations) and would drain the ring at every step
       __asm__ volatile("" ::: "memory");
       __builtin_amdgcn_s_barrier();
       __asm__ volatile("" ::: "memory");
-      if (t + NST - 1 < steps) load_step(t + NST - 1, (int)((t + NST - 1) % NST));
-      const unsigned char *sA = lds_w + (int)(t % NST) * STAGE, *sB = sA + BM * ROWB;
-      bf16x8 a[BK / 16][FM], b[BK / 16][FN];
+    };
+    int rslot = 0, lslot = AHEAD;  // stage of step u, stage that receives step u + AHEAD
+    // phase u: X holds step u - 1's fragments, Y receives step u's
+    auto phase = [&](bf16x8 (&X)[2][8], bf16x8 (&Y)[2][8]) {
+      rslot = rslot + 1 == NST ? 0 : rslot + 1;
+      lslot = lslot + 1 == NST ? 0 : lslot + 1;
+      wait_vm<(AHEAD - 1) * LOADS>();  // step u's loads (AHEAD - 1 later steps may be pending)
+      wait_lds();                      // this wave's reads of step u - 1 (slot lslot) are done
+      bar();
+      __builtin_amdgcn_sched_barrier(0);
+      mfmas(X, 0, PRE);
+      __builtin_amdgcn_sched_barrier(0);
+      load_next(lslot);
+      const int sbase = rslot * STAGE;
 #pragma unroll
-      for (int ks = 0; ks < BK / 16; ++ks) {
-        const int c = 2 * ks + (lane >> 5);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-          a[ks][i] = *(const bf16x8 *)(sA + (wm * 128 + i * 32 + fr) * ROWB + ((c ^ fsw) << 4));
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          b[ks][j] = *(const bf16x8 *)(sB + (wn * 128 + j * 32 + fr) * ROWB + ((c ^ fsw) << 4));
+      for (int q = 0; q < 16; ++q) {
+        __builtin_amdgcn_sched_barrier(0);
+        read_one(sbase, Y, q);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(X, PRE + (q * SPAN) / 16, PRE + ((q + 1) * SPAN) / 16);
       }
       __builtin_amdgcn_sched_barrier(0);
+      mfmas(X, PRE + SPAN, 32);
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    __syncthreads();  // the previous tile's readers are done with LDS
+    if (steps > 0) {
+      bf16x8 F[2][8], Gr[2][8];
 #pragma unroll
-      for (int ks = 0; ks < BK / 16; ++ks)
+      for (int q = 0; q < AHEAD; ++q) load_next(q);
+      wait_vm<(AHEAD - 1) * LOADS>();
+      bar();
+      load_next(AHEAD);
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks][i], b[ks][j], acc[i][j], 0, 0, 0);
+      for (int q = 0; q < 16; ++q) read_one(0, F, q);
+      // phases 1 .. steps - 1, two per trip so the register sets swap roles without copies
+      for (int u = 1; u + 1 < steps; u += 2) {
+        phase(F, Gr);
+        phase(Gr, F);
+      }
+      if (EVEN) {
+        phase(F, Gr);
+        mfmas(Gr, 0, 32);
+      } else {
+        mfmas(F, 0, 32);
+      }
+      wait_vm<0>();  // the loads past the last step have landed before LDS is reused
     }
-    store_c_nt<BM, BN, 2, 2>(p, row0, col0, acc);
+    store_c_nt<256, 256, 2, 2, !ALIGNED>(p, row0, col0, acc);
   });
 }
 
@@ -645,9 +702,13 @@ hipError_t launch_matmul_mfma(const MatmulP &p, const LoopK &, const SchedK &S, 
     // whole tiles and whole k-panels: no bounds tests in the load loop
     const bool al = p.M % 256 == 0 && p.N % 256 == 0 && p.K % MMW_BK == 0;
     const size_t lds = MMW_STAGES * MMW_STAGE;
-    if (p.kind == UPIR_BODY_MATMUL_BF16)
-      return al ? go_mm(k_mm_bf16_wide<1, true>, p, S, lds, st) : go_mm(k_mm_bf16_wide<1, false>, p, S, lds, st);
-    return al ? go_mm(k_mm_bf16_wide<3, true>, p, S, lds, st) : go_mm(k_mm_bf16_wide<3, false>, p, S, lds, st);
+    const bool even = (p.K + MMW_BK - 1) / MMW_BK % 2 == 0;  // NSEG x steps is even iff steps is
+    if (p.kind == UPIR_BODY_MATMUL_BF16) {
+      if (al) return even ? go_mm(k_mm_bf16_wide<1, true, true>, p, S, lds, st) : go_mm(k_mm_bf16_wide<1, true, false>, p, S, lds, st);
+      return even ? go_mm(k_mm_bf16_wide<1, false, true>, p, S, lds, st) : go_mm(k_mm_bf16_wide<1, false, false>, p, S, lds, st);
+    }
+    if (al) return even ? go_mm(k_mm_bf16_wide<3, true, true>, p, S, lds, st) : go_mm(k_mm_bf16_wide<3, true, false>, p, S, lds, st);
+    return even ? go_mm(k_mm_bf16_wide<3, false, true>, p, S, lds, st) : go_mm(k_mm_bf16_wide<3, false, false>, p, S, lds, st);
   }
   if (p.kind == UPIR_BODY_MATMUL_BF16) {
     if (bm == 256) return go_mm(k_mm_bf16<1, 256, 256, 2, 4, 64, 2>, p, S, 2 * (256 + 256) * 72 * 2, st);

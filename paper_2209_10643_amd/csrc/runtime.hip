@@ -711,16 +711,16 @@ void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sc
     case UPIR_BODY_MATMUL_BF16:
     case UPIR_BODY_MATMUL_SPLIT3: {
       // MFMA tile configurations: float32 128 x 128 on 4 wavefronts;
-      // bfloat16 256 x 256 on 4 wavefronts of 128 x 128 each; the split's
-      // three products 256 x 256 on 8 wavefronts (measured faster for it
-      // than the 4-wavefront tile over K' = 3K); 128 x 128 tiles for small C
+      // bfloat16 and the split's three products 256 x 256 on 4 wavefronts of
+      // 128 x 128 each (the split as one product over K' = 3K: 411 us against
+      // 446 us for the 8-wavefront tile at 4096^3); 128 x 128 tiles for small C
       const bool f32 = lp->kind == UPIR_BODY_MATMUL_F32;
       const bool small = lp->cnt[0] * lp->cnt[1] < 2048LL * 2048;
       const int t = f32 || small ? 128 : 256;
       sc.policy = UPIR_SCHED_STATIC;
       sc.tile[0] = t;
       sc.tile[1] = t;
-      sp.num_units = (t == 256 && lp->kind == UPIR_BODY_MATMUL_SPLIT3) ? 512 : 256;
+      sp.num_units = 256;
       sp.num_teams = 0;
       break;
     }

@@ -105,6 +105,25 @@ def test_mfma_chunked_team_schedule(ctx):
     assert bodies.frob_rel(got, bodies.matmul_bf16(A, B)) <= 1e-5
 
 
+@pytest.mark.parametrize("kind", ["bf16", "split"])
+@pytest.mark.parametrize("M,N,K,teams,chunked", [(512, 768, 96, 2, False), (512, 512, 128, 3, True),
+                                                 (640, 520, 160, 2, False), (768, 256, 32, 2, True)])
+def test_wide_tile_teams_with_several_tiles(ctx, kind, M, N, K, teams, chunked):
+    """The four-wavefront 256 x 256 tile when a team computes several tiles one
+    after another (the load ring restarts per tile), with odd and even numbers
+    of 32-wide k steps, whole and partial tiles."""
+    note(f"wide tile {kind} {M}x{N}x{K} teams={teams} chunked={chunked}")
+    A = synth.normal(33, 0, M * K).reshape(M, K)
+    B = synth.normal(33, 1, K * N).reshape(K, N)
+    sched = (H.make_sched(U.UPIR_SCHED_STATIC_CHUNK, 1, tile=(256, 256)) if chunked
+             else H.make_sched(U.UPIR_SCHED_STATIC, tile=(256, 256)))
+    got, variant = run_mm(ctx, kind, A, B, sched, H.make_spmd(teams, 256))
+    assert variant == "matmul_mfma"
+    ref = bodies.matmul_bf16(A, B) if kind == "bf16" else bodies.matmul_split3(A, B)
+    assert bodies.frob_rel(got, ref) <= 1e-5
+    assert bodies.frob_rel(got, bodies.matmul(A, B)) <= TOL[kind]
+
+
 @pytest.mark.parametrize("kind", ["f32", "bf16", "split"])
 def test_mfma_full_size_4096(ctx, kind):
     n = 4096
