@@ -712,10 +712,13 @@ void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sc
     case UPIR_BODY_MATMUL_SPLIT3: {
       // MFMA tile configurations: float32 128 x 128 on 4 wavefronts;
       // bfloat16 and the split's three products 256 x 256 on 4 wavefronts of
-      // 128 x 128 each (the split as one product over K' = 3K: 411 us against
-      // 446 us for the 8-wavefront tile at 4096^3); 128 x 128 tiles for small C
+      // 128 x 128 each (the split as one product over K' = 3K: 250 us against
+      // 355 us for the 8-wavefront tile at 4096^3); 128 x 128 tiles when C
+      // has fewer 256 x 256 tiles than half the device's CUs (measured with
+      // 256 CUs: 128 x 128 faster at 2048^2, 64 large tiles; 256 x 256 faster
+      // at 3072^2, 144 large tiles)
       const bool f32 = lp->kind == UPIR_BODY_MATMUL_F32;
-      const bool small = lp->cnt[0] * lp->cnt[1] < 2048LL * 2048;
+      const bool small = 2 * cdiv(lp->cnt[0], 256) * cdiv(lp->cnt[1], 256) < c->num_cus;
       const int t = f32 || small ? 128 : 256;
       sc.policy = UPIR_SCHED_STATIC;
       sc.tile[0] = t;
