@@ -311,11 +311,21 @@ def bench_stream_large(torch, ctx, timer, reps=10):
         ok &= bool(np.array_equal(yb[st:st + w].cpu().numpy(), want))
     for h in (lb, ls):
         ctx.free(h)
+    # context, not the product path: torch's own elementwise and reduction
+    # kernels on the same arrays (AXPY without the sum, a float32 sum, a copy)
+    ref = {}
+    for name, fn, nbytes in (("axpy_add_", lambda: yb.add_(xb, alpha=2.5), 12 * nb),
+                             ("sum", lambda: torch.sum(xb), 4 * nb),
+                             ("copy_", lambda: yb.copy_(xb), 8 * nb)):
+        fn()
+        ms = timer.time(fn, reps)
+        ref[name] = round(nbytes / (ms * 1e-3) / 1e9, 1)
     del xb, yb
     torch.cuda.empty_cache()
     ga, gs = 12 * nb / (msb * 1e-3) / 1e9, 4 * nb / (mss * 1e-3) / 1e9
     return {"large_n": nb, "large_GBps": round(ga, 1), "large_frac": round(ga / HBM_PEAK_GBS, 4),
             "large_sum_GBps": round(gs, 1), "large_sum_frac": round(gs / HBM_PEAK_GBS, 4),
+            "reference_torch_GBps": ref,
             "large_vs_oracle": {"y_bitexact_sampled": ok,
                                 "sample": "16 windows of 65536 outputs at seeded offsets (sums at this size are "
                                           "checked by the parity tests, not here)"}}

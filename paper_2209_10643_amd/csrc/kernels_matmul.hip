@@ -592,8 +592,8 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_f32(MatmulP p, SchedK S) {
   constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
   constexpr int CA = BM * (BK / 4) / NTH, CB = BK * (BN / 4) / NTH;
   static_assert(BM * (BK / 4) % NTH == 0 && BK * (BN / 4) % NTH == 0, "chunk split");
+  constexpr int STAGEF = BM * PA + BK * PB;  // floats per LDS stage (two stages)
   extern __shared__ __attribute__((aligned(16))) float ldsf[];
-  float *sA = ldsf, *sB = ldsf + BM * PA;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int64_t K = p.K;
@@ -620,7 +620,8 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_f32(MatmulP p, SchedK S) {
         rb[q] = (gk < K && gc < p.N) ? *(const f32x4v *)(p.B + gk * p.ldb + gc) : f32x4v{};
       }
     };
-    auto stage = [&]() {
+    auto stage = [&](int buf) {
+      float *sA = ldsf + buf * STAGEF, *sB = sA + BM * PA;
 #pragma unroll
       for (int q = 0; q < CA; ++q) {
         const int c = tid + q * NTH, r = c / (BK / 4), kc = c % (BK / 4);
@@ -632,14 +633,16 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_f32(MatmulP p, SchedK S) {
         *(f32x4v *)(sB + r * PB + nc * 4) = rb[q];
       }
     };
-    __syncthreads();
+    __syncthreads();  // the previous tile's readers are done with both stages
     fetch(0);
-    stage();
+    stage(0);
     __syncthreads();
     const int g = lane >> 5;
+    int cur = 0;
     for (int64_t k0 = 0; k0 < K; k0 += BK) {
       const bool more = k0 + BK < K;
       if (more) fetch(k0 + BK);
+      const float *sA = ldsf + cur * STAGEF, *sB = sA + BM * PA;
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 8) {
         // group g takes k = kk + 4g + s at MFMA step s (same for A and B)
@@ -659,11 +662,12 @@ __global__ void __launch_bounds__(WM * WN * 64) k_mm_f32(MatmulP p, SchedK S) {
               acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][s], b[j], acc[i][j], 0, 0, 0);
         }
       }
-      if (more) {
-        __syncthreads();
-        stage();
-        __syncthreads();
-      }
+      // the next step goes into the other stage; one barrier then both makes
+      // it visible and keeps this stage from being overwritten (two steps on)
+      // before every wave has read it
+      if (more) stage(cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
     }
     store_c<BM, BN, WM, WN>(p, row0, col0, acc);
   });
@@ -736,8 +740,9 @@ hipError_t launch_matmul_mfma(const MatmulP &p, const LoopK &, const SchedK &S, 
     if (bm == 256) return go_mm(k_mm_bf16<3, 256, 256, 2, 4, 32, 2>, p, S, 2 * 2 * (256 + 256) * 32 * 2, st);
     return go_mm(k_mm_bf16<3, 128, 128, 2, 2, 32, 2>, p, S, 2 * 2 * (128 + 128) * 32 * 2, st);
   }
-  if (bm == 256 && bn == 128) return go_mm(k_mm_f32<256, 128, 4, 2, 32>, p, S, (256 * 36 + 32 * 136) * 4, st);
-  return go_mm(k_mm_f32<128, 128, 2, 2, 32>, p, S, (128 * 36 + 32 * 136) * 4, st);
+  // two LDS stages of (BM x (BK + 4) + BK x (BN + 8)) floats
+  if (bm == 256 && bn == 128) return go_mm(k_mm_f32<256, 128, 4, 2, 32>, p, S, 2 * (256 * 36 + 32 * 136) * 4, st);
+  return go_mm(k_mm_f32<128, 128, 2, 2, 32>, p, S, 2 * (128 * 36 + 32 * 136) * 4, st);
 }
 
 }  // namespace upir
