@@ -241,11 +241,23 @@ __device__ __forceinline__ void st4(f32x4 *p, f32x4 v) {
 
 // OP is the reduction (RED_NONE for none), fixed at compile time so the
 // per-element fold is one instruction.
+// An earlier loop's deferred fold gets one extra workgroup, launched last and
+// given no chunks: it runs beside the others instead of after workgroup 0's
+// own chunks (which put the fold's memory round trips on the kernel's
+// critical path, about 2 us of a 4 us loop at 2^20). When this loop's own
+// reduction is synchronous, that workgroup is also the combiner.
 template <int BODY, int OP, bool NT>
 __global__ void __launch_bounds__(1024) k_stream4(int64_t n, float a, const float *__restrict__ x,
                                                   float *__restrict__ y, int32_t *__restrict__ cnt, RedK R) {
   constexpr bool RED = OP != RED_NONE;
-  const int64_t F = (int64_t)gridDim.x * blockDim.x;
+  const bool xwg = R.fold.count > 0;
+  const int G = xwg ? (int)gridDim.x - 1 : (int)gridDim.x;  // workgroups that take chunks
+  if (xwg && (int)blockIdx.x == G) {
+    run_fold(R.fold);
+    if (RED && !R.defer) finish_reduction<float>(R, red_identity<float>(OP));
+    return;
+  }
+  const int64_t F = (int64_t)G * blockDim.x;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nc = n >> 2;
   float acc = RED ? red_identity<float>(OP) : 0.0f;
@@ -314,7 +326,6 @@ __global__ void __launch_bounds__(1024) k_stream4(int64_t n, float a, const floa
       for (int64_t i = nc * 4; i < n; ++i) atomicAdd(&cnt[i], 1);
   }
   if (RED) finish_reduction<float>(R, acc);
-  fold_hook(R);
 }
 
 template <int BODY, int OP>
@@ -345,7 +356,7 @@ hipError_t launch_stream4(int32_t body, const void *payload, const LoopK &L, con
   // cache; below 64 MiB plain accesses are as fast or faster either way.
   const bool nt = (uint64_t)L.n * (body == 1 ? 8u : 4u) >= (64ull << 20);
   const int64_t n = L.n, lb = L.lb[0];
-  dim3 g(S.T), b(S.U);
+  dim3 g(S.T + (R.fold.count > 0 ? 1 : 0)), b(S.U);  // + the fold's own workgroup
   if (body == 1) {
     const AxpyP &p = *(const AxpyP *)payload;
     go_stream4_op<1>(nt, g, b, st, n, p.a, p.x + lb, p.y + lb, nullptr, R);
