@@ -166,16 +166,19 @@ hipError_t launch_bf16_split(const MatmulP &p, bool need_lo, hipStream_t st) {
 // within-tile assignment of points to units is fixed by the matrix cores.
 //
 // Waves form a WM x WN grid; each wave owns (BM/WM) x (BN/WN) of the tile as
-// 32 x 32 MFMA blocks. K advances in steps of BK: the next step's operands
-// are fetched from global memory into registers while the current step's
-// operands, staged in LDS with padded rows (no bank conflicts on the 16-byte
-// fragment reads), feed the matrix cores.
+// 32 x 32 MFMA blocks. K advances in steps of BK. In the tiles below
+// (k_mm_bf16, k_mm_f32) the next step's operands are fetched from global
+// memory into registers while the current step's operands, staged in LDS
+// (padded or swizzled rows: no bank conflicts on the fragment reads), feed
+// the matrix cores; the four-wave 256 x 256 tile further down
+// (k_mm_bf16_wide) loads straight into a ring of LDS stages instead.
 //
 // bfloat16 variants use v_mfma_f32_32x32x16_bf16 (lane l supplies row l%32
 // and 8 consecutive k of group l/32); both hi/lo operands come from the
-// pre-pass workspace (A as M x K, B transposed as N x K). The split variant
-// accumulates lo_A hi_B, hi_A lo_B and hi_A hi_B into one float32 sum.
-// float32 uses v_mfma_f32_32x32x2f32 over A (M x K) and B (K x N) directly.
+// pre-pass workspace (A as M x K, B transposed as N x K, or k-panels of 32
+// for the wide tile). The split variant accumulates lo_A hi_B, hi_A lo_B and
+// hi_A hi_B into one float32 sum. float32 uses v_mfma_f32_32x32x2f32 over A
+// (M x K) and B (K x N) directly.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
