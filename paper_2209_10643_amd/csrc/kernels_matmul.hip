@@ -421,6 +421,16 @@ __device__ inline void wait_vm() {
 // s_waitcnt lgkmcnt(0) (LDS reads of this wave complete), other counters at their maximum
 __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4)); }
 
+// The operands of one k step of the wide tile: buffer resources of the A
+// and B arrays it reads, their k-panel byte offsets (the loads' scalar
+// offsets), whether this lane's k chunk lies below K, and the LDS stage.
+struct MmwStep {
+  __amdgpu_buffer_rsrc_t ra, rb;
+  uint32_t sa, sb;
+  bool kin;
+  unsigned char *dst;
+};
+
 bool matmul_wide(const MatmulP &p, const SchedK &S) {
   return p.kind != UPIR_BODY_MATMUL_F32 && S.tile[0] == 256 && S.tile[1] == 256 && S.U == 256;
 }
@@ -479,26 +489,30 @@ __global__ void __launch_bounds__(256) k_mm_bf16_wide(MatmulP p, SchedK S) {
     }
     // the next step to load: its index, segment and k-panel (scalars)
     int lt = 0, lseg = 0, lkt = 0;
-    // load instruction idx (0..7: row group idx / 2, A if even, B if odd) of
-    // the step whose operands, panel offsets and k test are given, into the stage at dst
-    auto load_one = [&](__amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb, uint32_t sa, uint32_t sb, bool kin,
-                        unsigned char *dst, int idx) {
+    // the operands of step lt (segment for NSEG = 3, k-panel; steps past the
+    // end load panel 0) and the LDS stage that receives them
+    auto step_ops = [&](int slot) {
+      const bool live = lt < steps;
+      const int kt = live ? lkt : 0, seg = NSEG == 3 && live ? lseg : 0;
+      MmwStep o;
+      o.ra = seg == 0 ? ral : rah;
+      o.rb = seg == 1 ? rbl : rbh;
+      o.sa = (uint32_t)kt * pa;
+      o.sb = (uint32_t)kt * pb;
+      o.kin = ALIGNED || (int64_t)kt * MMW_BK + lc * 8 < K;
+      o.dst = lds_w + slot * STAGE + wv * 64 * ROWB;
+      return o;
+    };
+    // load instruction idx (0..7: row group idx / 2, A if even, B if odd)
+    auto load_one = [&](const MmwStep &o, int idx) {
       const bool isb = idx & 1;
       const int g = idx >> 1;
       // ragged shapes: rows past M or N and k past K read as zero
-      const uint32_t vo = ALIGNED || ((isb ? vb[g] : va[g]) && kin) ? (isb ? ob0[g] : oa0[g]) : 0x80000000u;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(isb ? rb : ra,
-                                               (__attribute__((address_space(3))) void *)(dst + (isb ? BM * ROWB : 0) + g * 16 * ROWB),
-                                               16, vo, isb ? sb : sa, 0, 0);
+      const uint32_t vo = ALIGNED || ((isb ? vb[g] : va[g]) && o.kin) ? (isb ? ob0[g] : oa0[g]) : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(isb ? o.rb : o.ra,
+                                               (__attribute__((address_space(3))) void *)(o.dst + (isb ? BM * ROWB : 0) + g * 16 * ROWB),
+                                               16, vo, isb ? o.sb : o.sa, 0, 0);
     };
-    // operands of step lt: segment (NSEG = 3), k-panel; steps past the end load panel 0
-#define MMW_STEP_OPERANDS(slot)                                                                    \
-  const bool live_ = lt < steps;                                                                   \
-  const int kt_ = live_ ? lkt : 0, seg_ = NSEG == 3 && live_ ? lseg : 0;                           \
-  const __amdgpu_buffer_rsrc_t ra_ = seg_ == 0 ? ral : rah, rb_ = seg_ == 1 ? rbl : rbh;           \
-  const uint32_t sa_ = (uint32_t)kt_ * pa, sb_ = (uint32_t)kt_ * pb;                              \
-  const bool kin_ = ALIGNED || (int64_t)kt_ * MMW_BK + lc * 8 < K;                                \
-  unsigned char *dst_ = lds_w + (slot) * STAGE + wv * 64 * ROWB;
     auto advance = [&] {
       ++lt;
       if (++lkt == seg_steps) {
@@ -507,9 +521,9 @@ __global__ void __launch_bounds__(256) k_mm_bf16_wide(MatmulP p, SchedK S) {
       }
     };
     auto load_next = [&](int slot) {
-      MMW_STEP_OPERANDS(slot)
+      const MmwStep o = step_ops(slot);
 #pragma unroll
-      for (int idx = 0; idx < LOADS; ++idx) load_one(ra_, rb_, sa_, sb_, kin_, dst_, idx);
+      for (int idx = 0; idx < LOADS; ++idx) load_one(o, idx);
       advance();
     };
     // fragment q of a step (k half q / 8; 0-3: A blocks, 4-7: B blocks) from the stage at byte sbase
@@ -545,12 +559,12 @@ __global__ void __launch_bounds__(256) k_mm_bf16_wide(MatmulP p, SchedK S) {
       __builtin_amdgcn_sched_barrier(0);
       mfmas(X, 0, PRE);
       const int sbase = rslot * STAGE;
-      MMW_STEP_OPERANDS(lslot)
+      const MmwStep o = step_ops(lslot);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         __builtin_amdgcn_sched_barrier(0);
         read_one(sbase, Y, q);
-        if (q & 1) load_one(ra_, rb_, sa_, sb_, kin_, dst_, q >> 1);
+        if (q & 1) load_one(o, q >> 1);
         __builtin_amdgcn_sched_barrier(0);
         mfmas(X, PRE + (q * SPAN) / 16, PRE + ((q + 1) * SPAN) / 16);
       }
@@ -585,7 +599,6 @@ __global__ void __launch_bounds__(256) k_mm_bf16_wide(MatmulP p, SchedK S) {
     store_c_nt<256, 256, 2, 2, !ALIGNED>(p, row0, col0, acc);
   });
 }
-#undef MMW_STEP_OPERANDS
 
 template <int BM, int BN, int WM, int WN, int BK>
 __global__ void __launch_bounds__(WM * WN * 64) k_mm_f32(MatmulP p, SchedK S) {
