@@ -2,8 +2,9 @@
 the loop kernel, wait-release at the next synchronisation point (sec. 5).
 
 A loop whose reduction has ``async = 1`` leaves one partial per wavefront;
-the fold runs in the next loop kernel on the context's stream (workgroup 0,
-or an extra workgroup of a Jacobi sweep), or as a one-workgroup kernel at
+the fold runs in the next loop kernel on the context's stream (an extra
+workgroup of a streaming loop or a Jacobi sweep, else workgroup 0 after its
+own work), or as a one-workgroup kernel at
 upir_sync / upir_reduce_wait / graph end / taskwait. Results must equal the synchronous path's: exact for max, min and
 integer sums, within the float sum bound otherwise.
 """
@@ -224,9 +225,9 @@ def test_tuning_an_async_loop_leaves_its_result_alone(ctx):
 
 @pytest.mark.parametrize("jacobi_red", ["sync", "none", "async"])
 def test_fold_rides_on_a_jacobi_sweep(ctx, jacobi_red):
-    """An async loop's fold carried by the next kernel, a Jacobi sweep: by an
-    extra workgroup when the sweep combines nothing across workgroups itself
-    (no reduction, or an async one), else by workgroup 0 after its tiles."""
+    """An async loop's fold carried by the next kernel, a Jacobi sweep: by the
+    sweep's extra workgroup, which is also the combiner when the sweep's own
+    reduction is synchronous."""
     note(f"fold on jacobi ({jacobi_red})")
     v = synth.uniform_pm1(21, 0, 70001)
     t = dev(v)
@@ -251,3 +252,41 @@ def test_fold_rides_on_a_jacobi_sweep(ctx, jacobi_red):
         assert r2.item() == (-1.0 if jacobi_red == "none" else want_r[0]), rep
     ctx.free(first)
     ctx.free(sweep)
+
+
+@pytest.mark.parametrize("stream_red", ["sync", "none", "async"])
+@pytest.mark.parametrize("spmd", [None, (3, 64), (37, 256)])
+def test_fold_rides_on_a_streaming_loop(ctx, stream_red, spmd):
+    """An async loop's fold carried by the next kernel, an AXPY streaming loop:
+    by one extra workgroup launched after the chunked ones, which is also the
+    combiner when the AXPY loop's own sum is synchronous."""
+    note(f"fold on axpy ({stream_red}, spmd {spmd})")
+    v = synth.uniform_pm1(23, 0, 70001)
+    t = dev(v)
+    r1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    first = ctx.loop(U.UPIR_BODY_SUM, U.upir_sum_args(t.data_ptr(), U.UPIR_DT_F32, 0), [(0, len(v), 1)], None,
+                     H.make_red(U.UPIR_RED_MAX, r1.data_ptr(), async_=True))
+    n = 100003
+    x, y0 = synth.uniform_pm1(24, 0, n), synth.uniform_pm1(24, 1, n)
+    tx, ty = dev(x), dev(y0)
+    r2 = torch.full((1,), -7.0, dtype=torch.float64, device="cuda")
+    red = None if stream_red == "none" else H.make_red(U.UPIR_RED_SUM, r2.data_ptr(), async_=(stream_red == "async"))
+    ax = ctx.loop(U.UPIR_BODY_AXPY, U.upir_axpy_args(2.5, 0, tx.data_ptr(), ty.data_ptr()), [(0, n, 1)], None, red)
+    sp = H.make_spmd(*spmd) if spmd else None
+    assert U.VARIANTS[ctx.resolve(ax, sp)[2]] == "stream4"
+    want_y = bodies.axpy(2.5, x, y0)
+    for rep in range(2):
+        r1.zero_()
+        r2.fill_(-7.0)
+        ty.copy_(dev(y0))
+        ctx.launch(first)
+        ctx.launch(ax, sp)
+        ctx.sync()
+        assert r1.item() == float(v.max()), rep
+        assert np.array_equal(ty.cpu().numpy(), want_y), rep
+        if stream_red == "none":
+            assert r2.item() == -7.0, rep
+        else:
+            assert abs(r2.item() - bodies.sum_f64(want_y)) <= 1e-5 * bodies.sum_abs_f64(want_y), rep
+    ctx.free(first)
+    ctx.free(ax)
