@@ -83,9 +83,9 @@ struct ModelState;  // cost model (learned.hip)
 
 // Deferred reduction folds (async reductions): a launch leaves one partial
 // per wavefront in fold_buf[fold_flip] and flips; the fold is run by the
-// next loop kernel on the stream (workgroup 0, or an extra workgroup of a
-// Jacobi sweep), or by a one-workgroup kernel at the next synchronisation
-// point. Two buffers, so a kernel can fold its predecessor's partials while
+// next loop kernel on the stream (an extra workgroup of a streaming loop or
+// a Jacobi sweep, else workgroup 0 after its own work), or by a
+// one-workgroup kernel at the next synchronisation point. Two buffers, so a kernel can fold its predecessor's partials while
 // writing its own.
 struct PendingFold {
   bool on = false;

@@ -518,8 +518,9 @@ __host__ __device__ inline bool jacobi_extra_wg(const RedK &R) {
 }
 
 // Called by every thread at the very end of a loop kernel: workgroup 0 runs
-// the fold an earlier loop deferred (after its own work, off the path of
-// the workgroups still running).
+// the fold an earlier loop deferred, after its own work. (The streaming and
+// Jacobi kernels give the fold an extra workgroup instead, which runs beside
+// the others rather than at the end of workgroup 0.)
 __device__ inline void fold_hook(const RedK &R) {
   if (R.fold.count > 0 && blockIdx.x == 0) run_fold(R.fold);
 }
