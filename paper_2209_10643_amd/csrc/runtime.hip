@@ -710,21 +710,26 @@ void default_choice(upir_ctx *c, const upir_loop_obj *lp, upir_spmd &sp, upir_sc
     case UPIR_BODY_MATMUL_F32:
     case UPIR_BODY_MATMUL_BF16:
     case UPIR_BODY_MATMUL_SPLIT3: {
-      // MFMA tile configurations: float32 128 x 128 on 4 wavefronts;
-      // bfloat16 and the split's three products 256 x 256 on 4 wavefronts of
-      // 128 x 128 each (the split as one product over K' = 3K: 250 us against
-      // 355 us for the 8-wavefront tile at 4096^3); 128 x 128 tiles when C
-      // has fewer 256 x 256 tiles than half the device's CUs (measured with
-      // 256 CUs: 128 x 128 faster at 2048^2, 64 large tiles; 256 x 256 faster
-      // at 3072^2, 144 large tiles)
-      const bool f32 = lp->kind == UPIR_BODY_MATMUL_F32;
-      const bool small = 2 * cdiv(lp->cnt[0], 256) * cdiv(lp->cnt[1], 256) < c->num_cus;
-      const int t = f32 || small ? 128 : 256;
+      // MFMA tile configurations: bfloat16 and the split's three products
+      // 256 x 256 on 4 wavefronts of 128 x 128 each (the split as one product
+      // over K' = 3K: 250 us against 355 us for the 8-wavefront tile at
+      // 4096^3); 128 x 128 tiles when C has fewer 256 x 256 tiles than half
+      // the device's CUs (measured with 256 CUs: 128 x 128 faster at 2048^2,
+      // 64 large tiles; 256 x 256 faster at 3072^2, 144 large tiles).
+      // float32: 256 x 128 on 8 wavefronts when C has at least one such tile
+      // per CU (1.08 against 1.11 ms at 4096^3), else 128 x 128 on 4.
       sc.policy = UPIR_SCHED_STATIC;
-      sc.tile[0] = t;
-      sc.tile[1] = t;
-      sp.num_units = 256;
       sp.num_teams = 0;
+      sp.num_units = 256;
+      if (lp->kind == UPIR_BODY_MATMUL_F32) {
+        const bool big = cdiv(lp->cnt[0], 256) * cdiv(lp->cnt[1], 128) >= c->num_cus;
+        sc.tile[0] = big ? 256 : 128;
+        sc.tile[1] = 128;
+        sp.num_units = big ? 512 : 256;
+        break;
+      }
+      const bool small = 2 * cdiv(lp->cnt[0], 256) * cdiv(lp->cnt[1], 256) < c->num_cus;
+      sc.tile[0] = sc.tile[1] = small ? 128 : 256;
       break;
     }
     case UPIR_BODY_MATVEC:
