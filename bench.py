@@ -822,6 +822,9 @@ def bench_batched(torch, ctx, timer, reps=3, have_model=False):
     res["speedup_vs_plain_graph"] = round(res["plain_graph_ms"] / res["batched_ms"], 2)
     res["GBps_batched"] = round(bytes_alg / (res["batched_ms"] * 1e-3) / 1e9, 1)
     res["frac"] = round(res["GBps_batched"] / HBM_PEAK_GBS, 4)
+    # the batched + learned form (the engine schedule that taskwait picks by itself)
+    res["GBps_batched_learned"] = round(bytes_alg / (res["batched_learned_ms"] * 1e-3) / 1e9, 1)
+    res["frac_learned"] = round(res["GBps_batched_learned"] / HBM_PEAK_GBS, 4)
     res["algorithmic_GB"] = round(bytes_alg / 1e9, 3)
     res["tasks"] = len(tasks)
     res["edges"] = int(sum(len(p) for p in preds))
