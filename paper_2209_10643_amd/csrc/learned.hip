@@ -847,6 +847,9 @@ void batch_features(const upir_ctx *c, const upir_engine_sched &es, float f[32])
   f[30] = 1.0f;
 }
 
+// Cost model pick of the engine schedule for the pending task graph: one
+// forward pass over the 27 candidates, then a tile per body (below).
+// Returns false when the model is off.
 bool model_pick_engine(upir_ctx *c, upir_engine_sched &es) {
   if (!c->model || !c->model_on || c->capturing || c->no_alloc || c->tasks.empty()) return false;
   const auto cs = engine_candidates();
