@@ -848,8 +848,8 @@ void batch_features(const upir_ctx *c, const upir_engine_sched &es, float f[32])
 }
 
 // Cost model pick of the engine schedule for the pending task graph: one
-// forward pass over the 27 candidates, then a tile per body (below).
-// Returns false when the model is off.
+// forward pass over the 27 candidates, then the choice below. Returns false
+// when the model is off.
 bool model_pick_engine(upir_ctx *c, upir_engine_sched &es) {
   if (!c->model || !c->model_on || c->capturing || c->no_alloc || c->tasks.empty()) return false;
   const auto cs = engine_candidates();
@@ -864,12 +864,29 @@ bool model_pick_engine(upir_ctx *c, upir_engine_sched &es) {
   upir_dfree(c, dX);
   upir_dfree(c, dY);
   if (!ok) return false;
-  // Each body's tile is the choice whose candidates have the lowest mean
-  // prediction over the other bodies' choices. The features make a choice's
-  // effect close to additive over bodies, and the mean over nine
-  // predictions damps the model's error on any single candidate (the argmin
-  // over single candidates, on the benchmark's graph, sometimes took a
-  // matvec tile 3% slower than the default).
+  // The model ranks the schedules the exhaustive batch tuner has found best
+  // on some task graph it has tuned in this context, and the default: on
+  // its own the model's error is of the order of the differences it has to
+  // rank (the candidates of a large graph lie within a few percent of each
+  // other), and its argmin sometimes took a schedule no tuned graph ever
+  // preferred, slower than the default. Without tuned graphs, each body
+  // takes the tile whose candidates have the lowest mean prediction over
+  // the other bodies' choices (nine predictions per mean).
+  auto same = [](const upir_engine_sched &a, const upir_engine_sched &b) {
+    return a.tile_axpy == b.tile_axpy && a.tile_sum == b.tile_sum && a.rows_matvec == b.rows_matvec;
+  };
+  int pick = -1, seen = 0;
+  for (size_t i = 0; i < cs.size(); ++i) {
+    bool ok_i = i == 0;  // the default
+    for (const auto &kv : c->tuned_engine) ok_i = ok_i || same(kv.second.first, cs[i]);
+    if (!ok_i) continue;
+    seen += i > 0;
+    if (pick < 0 || y[i] < y[(size_t)pick]) pick = (int)i;
+  }
+  if (seen > 0) {
+    es = cs[(size_t)pick];
+    return true;
+  }
   double sum[3][3] = {}, cnt[3][3] = {};
   for (size_t i = 0; i < cs.size(); ++i)
     for (int k = 0; k < 3; ++k) {
