@@ -864,22 +864,36 @@ bool model_pick_engine(upir_ctx *c, upir_engine_sched &es) {
   upir_dfree(c, dX);
   upir_dfree(c, dY);
   if (!ok) return false;
-  // The model ranks the schedules the exhaustive batch tuner has found best
-  // on some task graph it has tuned in this context, and the default: on
-  // its own the model's error is of the order of the differences it has to
-  // rank (the candidates of a large graph lie within a few percent of each
-  // other), and its argmin sometimes took a schedule no tuned graph ever
-  // preferred, slower than the default. Without tuned graphs, each body
-  // takes the tile whose candidates have the lowest mean prediction over
-  // the other bodies' choices (nine predictions per mean).
+  // The model ranks the schedules the exhaustive batch tuner found best on
+  // the (up to) ten tuned graphs most like this one, and the default.
+  // Graphs are compared by their candidate-independent features (task and
+  // byte shares per body, task count, bytes, lengths, edges, depth). On its
+  // own the model's error is of the order of the differences it has to rank
+  // (the candidates of a large graph lie within a few percent of each
+  // other): its argmin over all 27 sometimes took a schedule that tuned
+  // graphs of another kind preferred (smaller graphs favour smaller matvec
+  // tiles), slower than the default. Without tuned graphs, each body takes
+  // the tile whose candidates have the lowest mean prediction over the
+  // other bodies' choices (nine predictions per mean).
   auto same = [](const upir_engine_sched &a, const upir_engine_sched &b) {
     return a.tile_axpy == b.tile_axpy && a.tile_sum == b.tile_sum && a.rows_matvec == b.rows_matvec;
   };
+  std::vector<std::pair<float, upir_engine_sched>> near;
+  for (const auto &kv : c->tuned_engine) {
+    auto g = c->tuned_engine_graph.find(kv.first);
+    if (g == c->tuned_engine_graph.end()) continue;
+    float d = 0.0f;
+    for (int q = 0; q < 12; ++q) d += (g->second[(size_t)q] - X[(size_t)q]) * (g->second[(size_t)q] - X[(size_t)q]);
+    near.emplace_back(d, kv.second.first);
+  }
+  const size_t kn = std::min<size_t>(10, near.size());
+  std::partial_sort(near.begin(), near.begin() + (ptrdiff_t)kn, near.end(),
+                    [](const auto &a, const auto &b) { return a.first < b.first; });
   int pick = -1, seen = 0;
   for (size_t i = 0; i < cs.size(); ++i) {
-    bool ok_i = i == 0;  // the default
-    for (const auto &kv : c->tuned_engine) ok_i = ok_i || same(kv.second.first, cs[i]);
-    if (!ok_i) continue;
+    bool in = i == 0;  // candidate 0, the default, always takes part
+    for (size_t j = 0; j < kn && !in; ++j) in = same(near[j].second, cs[i]);
+    if (!in) continue;
     seen += i > 0;
     if (pick < 0 || y[i] < y[(size_t)pick]) pick = (int)i;
   }

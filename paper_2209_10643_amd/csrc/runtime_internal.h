@@ -5,6 +5,7 @@
 #include <map>
 #include <set>
 #include <string>
+#include <array>
 #include <unordered_map>
 #include <vector>
 
@@ -127,6 +128,7 @@ struct upir_ctx {
   bool engine_set = false;               // the caller fixed the engine schedule
   upir_engine_sched engine_sched{};      // ... to this
   std::unordered_map<uint64_t, std::pair<upir_engine_sched, double>> tuned_engine;  // batch key -> best, us
+  std::unordered_map<uint64_t, std::array<float, 12>> tuned_engine_graph;           // batch key -> graph features
   void *noalloc_scratch = nullptr;       // this device's static scratch (upir_reduce_noalloc)
   bool no_alloc = false;                 // inside a call that must not allocate (AUTO skips the model)
 };

@@ -767,6 +767,9 @@ extern "C" upir_status upir_tune_batched(upir_ctx *c, int32_t reps, upir_engine_
   for (TuneRow &r : rows) r.log2_us -= base;
   c->db.insert(c->db.end(), rows.begin(), rows.end());
   c->tuned_engine[key] = std::make_pair(cs[bi], bus);
+  std::array<float, 12> gf;  // the candidate-independent graph features (slots 0-11)
+  for (int q = 0; q < 12; ++q) gf[(size_t)q] = rows[0].feat[q];
+  c->tuned_engine_graph[key] = gf;
   if (best) *best = cs[bi];
   if (best_us) *best_us = bus;
   return UPIR_OK;
