@@ -516,6 +516,9 @@ def test_graph_replay_after_scratch_growth(ctx):
     (1000, 256, None, None), (37, 100, None, None), (513, 300, None, None),
     (1000, 256, H.make_sched(U.UPIR_SCHED_STATIC), H.make_spmd(5, 128)),
     (999, 256, H.make_sched(U.UPIR_SCHED_STATIC_CHUNK, 3), H.make_spmd(7, 256)),
+    # rows of at least four 256-column blocks: eight / four blocks per trip, then one at a time
+    (300, 1024, None, None), (129, 2316, None, None), (64, 4096, None, None), (33, 3003, None, None),
+    (70, 2560, H.make_sched(U.UPIR_SCHED_STATIC), H.make_spmd(3, 128)),
 ])
 def test_matvec_parity(ctx, rows, cols, sched, spmd):
     A = synth.uniform_pm1(11, 0, rows * cols).reshape(rows, cols)
@@ -551,6 +554,32 @@ def test_matvec_schedules_bitwise_equal(ctx):
         outs.append(ty.cpu().numpy())
         ctx.free(lp)
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("cols", [2316, 4096])
+def test_matvec_wide_rows_loop_and_engine_bitwise(ctx, cols):
+    """Rows of many 256-column blocks: the loop kernel (blocks loaded eight or
+    four at a time) and the batched engine (one block at a time) add the same
+    products in the same order, so their outputs are identical bits."""
+    rows = 200
+    A = synth.uniform_pm1(13, 0, rows * cols).reshape(rows, cols)
+    x = synth.uniform_pm1(13, 1, cols)
+    tA, tx = dev(A), dev(x)
+    outs = []
+    for mode in ("loop", "engine"):
+        ty = torch.zeros(rows, device="cuda")
+        args = U.upir_matvec_args(tA.data_ptr(), tx.data_ptr(), ty.data_ptr(), cols, cols)
+        lp = ctx.loop(U.UPIR_BODY_MATVEC, args, [(0, rows, 1)], None)
+        if mode == "loop":
+            ctx.launch(lp)
+        else:
+            ctx.task(lp)
+            ctx.taskwait(U.UPIR_TASKWAIT_BATCHED)
+        ctx.sync()
+        outs.append(ty.cpu().numpy())
+        ctx.free(lp)
+    assert np.array_equal(outs[0], outs[1])
+    assert bodies.frob_rel(outs[0].astype(np.float64), bodies.matvec(A, x)) <= 1e-5
 
 
 # ---------------------------------------------------------- data mapping ----
