@@ -42,6 +42,7 @@ PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "split": 2500.0}
 # fp32 fused multiply-adds on the vector ALUs without packed math (which the
 # library's kernels do not emit): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 FP32_VECTOR_TFLOPS = 78.6
+PCIE_PEAK_GBS = 64.0  # PCIe 5.0 x16, one direction
 
 
 def log(*a):
@@ -535,6 +536,9 @@ def bench_pipeline(torch, ctx, n=1 << 26, chunks=16, reps=3):
     out.update({"n": n, "chunks": chunks, "bytes_moved": 12 * n,
                 "speedup": round(out["serial_ms"] / out["pipelined_ms"], 3),
                 "link_GBps_pipelined": round(12 * n / (out["pipelined_ms"] * 1e-3) / 1e9, 1)})
+    # x and y go in (8 B per element) while y comes out (4 B): against PCIe
+    # 5.0 x16's 64 GB/s per direction, both directions busy at once
+    out["frac_pcie"] = round(out["link_GBps_pipelined"] / (2 * PCIE_PEAK_GBS), 4)
     return out
 
 
