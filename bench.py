@@ -1081,7 +1081,8 @@ def main():
     extras["jacobi"] = {"grid": [4096, 4096], "sweeps": 100, "variant": jw.variant, "tile": list(jw.tile),
                         "schedule": "auto (exhaustive tuner)", "tuned_sweep_us": jw.tuned_us,
                         "teams": jw.teams, "units": jw.units, "res_first": float(res[0]), "res_last": float(res[-1]),
-                        "working_set_MiB": 128, "note": "two 64 MiB grids fit the 256 MB MALL"}
+                        "working_set_MiB": 128, "note": "two 64 MiB grids fit the 256 MB MALL",
+                        "frac_step": round(value / HBM_PEAK_GBS, 4)}
 
     if "1L" in configs:
         log("jacobi 16384^2 (beyond the MALL)")
