@@ -113,9 +113,18 @@ __device__ inline float2 ld2(const float *p) {
 }
 
 // 16-byte accesses through a buffer resource over one tile's range (the
-// resource's record count also bounds the accesses to the tile).
+// resource's record count also bounds the accesses to the tile). A tile is
+// run by the whole workgroup, so base and size are the same in every lane;
+// the task descriptor they come from is read with vector loads, though, and
+// the compiler would wrap every access through a resource it cannot prove
+// uniform in a per-lane loop. Taking both from the first active lane makes
+// the resource scalar.
 __device__ inline __amdgpu_buffer_rsrc_t tile_rsrc(const void *base, int64_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, 0x00020000);
+  const uint64_t b = (uint64_t)base;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  const int n = __builtin_amdgcn_readfirstlane((int)bytes);
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), (short)0, n, 0x00020000);
 }
 template <int MEM>
 __device__ inline f32x4e ld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
