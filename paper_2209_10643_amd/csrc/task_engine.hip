@@ -469,7 +469,8 @@ using namespace upir;
 // default (16384 elements, 64 KiB of each array, or 64 MATVEC rows).
 static int64_t task_tile(upir_loop_obj *lp, const upir_engine_sched &es) {
   if (lp->sched.tile[0] > 0) return lp->sched.tile[0];
-  const upir_engine_sched &use = lp->sched.policy == UPIR_SCHED_AUTO ? es : engine_candidates()[0];
+  // a copy: engine_candidates() returns a temporary
+  const upir_engine_sched use = lp->sched.policy == UPIR_SCHED_AUTO ? es : engine_candidates()[0];
   switch (lp->kind) {
     case UPIR_BODY_MATVEC: return use.rows_matvec;
     case UPIR_BODY_SUM: return use.tile_sum;
