@@ -52,9 +52,15 @@ def make_workload(seed, n, lmin=8, lmax=16, p_edge=None):
 
 
 def build_tasks(ctx, specs, preds, tile=0):
+    """tile: 0 for the default (AUTO) schedule, n > 0 for AUTO with an n-element
+    tile, "static" for a STATIC schedule without a tile (the engine then
+    takes its default tiles rather than the graph's engine schedule)."""
     tok = torch.zeros(len(specs), dtype=torch.int64, device="cuda")
     handles, bufs = [], []
-    sched = H.make_sched(U.UPIR_SCHED_AUTO, tile=(tile,)) if tile else None
+    if tile == "static":
+        sched = H.make_sched(U.UPIR_SCHED_STATIC)
+    else:
+        sched = H.make_sched(U.UPIR_SCHED_AUTO, tile=(tile,)) if tile else None
     for j, (kind, a) in enumerate(specs):
         if kind == "axpy":
             tx, ty = dev(a["x"]), dev(a["y"])
@@ -112,7 +118,7 @@ def stamps_ok(preds, start, done):
 
 
 @pytest.mark.parametrize("mode", [U.UPIR_TASKWAIT_PLAIN, U.UPIR_TASKWAIT_BATCHED])
-@pytest.mark.parametrize("seed,n,tile", [(1, 64, 0), (2, 200, 0), (3, 200, 4096)])
+@pytest.mark.parametrize("seed,n,tile", [(1, 64, 0), (2, 200, 0), (3, 200, 4096), (4, 120, "static")])
 def test_tasks_match_oracle(ctx, mode, seed, n, tile):
     note(f"tasks mode={mode} seed={seed} n={n} tile={tile}")
     specs, preds = make_workload(seed, n)
