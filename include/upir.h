@@ -365,8 +365,9 @@ upir_status upir_tune_db_row(upir_ctx *ctx, int64_t row, float *feat32, float *l
  * rows per tile for MATVEC tasks. A task graph resolves it, in order, to
  * the schedule the caller set, the exhaustive batch tuner's best for a graph
  * of the same shape, the cost model's choice (among the tuner's best
- * schedules of the ten tuned graphs most like this one, and the default),
- * or the default {16384, 16384, 64}. The candidates are the 27 combinations of AXPY
+ * schedules of the ten tuned graphs most like this one, and the default,
+ * the one with the lowest sum of the model's prediction and its mean time
+ * measured on those graphs), or the default {16384, 16384, 64}. The candidates are the 27 combinations of AXPY
  * {8192, 16384, 32768}, SUM {16384, 32768, 65536} and MATVEC {32, 64, 128};
  * candidate 0 is the default. */
 typedef struct { int64_t tile_axpy, tile_sum, rows_matvec; } upir_engine_sched;

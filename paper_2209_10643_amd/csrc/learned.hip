@@ -864,38 +864,61 @@ bool model_pick_engine(upir_ctx *c, upir_engine_sched &es) {
   upir_dfree(c, dX);
   upir_dfree(c, dY);
   if (!ok) return false;
-  // The model ranks the schedules the exhaustive batch tuner found best on
-  // the (up to) ten tuned graphs most like this one, and the default.
+  // The choice is among the schedules the exhaustive batch tuner found best
+  // on the (up to) ten tuned graphs most like this one, and the default.
   // Graphs are compared by their candidate-independent features (task and
-  // byte shares per body, task count, bytes, lengths, edges, depth). On its
-  // own the model's error is of the order of the differences it has to rank
-  // (the candidates of a large graph lie within a few percent of each
-  // other): its argmin over all 27 sometimes took a schedule that tuned
-  // graphs of another kind preferred (smaller graphs favour smaller matvec
-  // tiles), slower than the default. Without tuned graphs, each body takes
-  // the tile whose candidates have the lowest mean prediction over the
-  // other bodies' choices (nine predictions per mean).
+  // byte shares per body, task count, bytes, lengths, edges, depth). Each
+  // such schedule is scored by the model's prediction plus the mean of its
+  // measured log2(time / default) over those graphs (the tuner timed every
+  // candidate on them). On its own the model's error is of the order of the
+  // differences it has to rank (the candidates of a large graph lie within
+  // a few percent of each other): its argmin over all 27 sometimes took a
+  // schedule that tuned graphs of another kind preferred (smaller graphs
+  // favour smaller matvec tiles), and ranking only the nearest graphs' best
+  // schedules by the prediction still flipped between two of them from one
+  // trained model to the next. Without tuned graphs, each body takes the
+  // tile whose candidates have the lowest mean prediction over the other
+  // bodies' choices (nine predictions per mean).
   auto same = [](const upir_engine_sched &a, const upir_engine_sched &b) {
     return a.tile_axpy == b.tile_axpy && a.tile_sum == b.tile_sum && a.rows_matvec == b.rows_matvec;
   };
-  std::vector<std::pair<float, upir_engine_sched>> near;
+  struct Near {
+    float d;
+    upir_engine_sched best;
+    const std::vector<float> *rel;
+  };
+  std::vector<Near> near;
   for (const auto &kv : c->tuned_engine) {
     auto g = c->tuned_engine_graph.find(kv.first);
     if (g == c->tuned_engine_graph.end()) continue;
+    auto r = c->tuned_engine_rel.find(kv.first);
     float d = 0.0f;
     for (int q = 0; q < 12; ++q) d += (g->second[(size_t)q] - X[(size_t)q]) * (g->second[(size_t)q] - X[(size_t)q]);
-    near.emplace_back(d, kv.second.first);
+    near.push_back(Near{d, kv.second.first,
+                        r != c->tuned_engine_rel.end() && r->second.size() == cs.size() ? &r->second : nullptr});
   }
   const size_t kn = std::min<size_t>(10, near.size());
   std::partial_sort(near.begin(), near.begin() + (ptrdiff_t)kn, near.end(),
-                    [](const auto &a, const auto &b) { return a.first < b.first; });
+                    [](const Near &a, const Near &b) { return a.d < b.d; });
   int pick = -1, seen = 0;
+  float pick_score = 0.0f;
   for (size_t i = 0; i < cs.size(); ++i) {
     bool in = i == 0;  // candidate 0, the default, always takes part
-    for (size_t j = 0; j < kn && !in; ++j) in = same(near[j].second, cs[i]);
+    for (size_t j = 0; j < kn && !in; ++j) in = same(near[j].best, cs[i]);
     if (!in) continue;
     seen += i > 0;
-    if (pick < 0 || y[i] < y[(size_t)pick]) pick = (int)i;
+    double m = 0.0;
+    int nm = 0;
+    for (size_t j = 0; j < kn; ++j)
+      if (near[j].rel) {
+        m += (*near[j].rel)[i];
+        ++nm;
+      }
+    const float score = y[i] + (nm ? (float)(m / nm) : 0.0f);
+    if (pick < 0 || score < pick_score) {
+      pick = (int)i;
+      pick_score = score;
+    }
   }
   if (seen > 0) {
     es = cs[(size_t)pick];

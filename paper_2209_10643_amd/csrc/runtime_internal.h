@@ -129,6 +129,7 @@ struct upir_ctx {
   upir_engine_sched engine_sched{};      // ... to this
   std::unordered_map<uint64_t, std::pair<upir_engine_sched, double>> tuned_engine;  // batch key -> best, us
   std::unordered_map<uint64_t, std::array<float, 12>> tuned_engine_graph;           // batch key -> graph features
+  std::unordered_map<uint64_t, std::vector<float>> tuned_engine_rel;  // batch key -> log2(time / default) per candidate
   void *noalloc_scratch = nullptr;       // this device's static scratch (upir_reduce_noalloc)
   bool no_alloc = false;                 // inside a call that must not allocate (AUTO skips the model)
 };

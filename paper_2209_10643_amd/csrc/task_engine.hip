@@ -780,6 +780,9 @@ extern "C" upir_status upir_tune_batched(upir_ctx *c, int32_t reps, upir_engine_
   std::array<float, 12> gf;  // the candidate-independent graph features (slots 0-11)
   for (int q = 0; q < 12; ++q) gf[(size_t)q] = rows[0].feat[q];
   c->tuned_engine_graph[key] = gf;
+  std::vector<float> rel(rows.size());
+  for (size_t i = 0; i < rows.size(); ++i) rel[i] = rows[i].log2_us;
+  c->tuned_engine_rel[key] = rel;
   if (best) *best = cs[bi];
   if (best_us) *best_us = bus;
   return UPIR_OK;
