@@ -24,3 +24,20 @@ def gpu_available() -> bool:
 @pytest.fixture(scope="session")
 def golden_dir():
     return os.path.join(ROOT, "tests", "golden")
+
+
+# Modules whose assertions are about measured speed of a model trained on
+# live timings (the learned schedule) run after the parity tests, and the
+# no-alloc entry point's tests (test_zz_*) stay last: under -x a timing
+# result that falls short stops the run without hiding the parity results.
+_LATE = ("test_gpu_learned.py",)
+
+
+def pytest_collection_modifyitems(config, items):
+    def rank(item):
+        name = item.fspath.basename
+        if name.startswith("test_zz_"):
+            return 2
+        return 1 if name in _LATE else 0
+
+    items[:] = sorted(items, key=rank)  # stable: the order within each group is kept
